@@ -1,0 +1,225 @@
+"""Seeded, synthetic workload descriptions for the coupled LB phase-field step.
+
+This module only *describes* inputs: grid, lattice pair, physical parameters,
+seeds and per-crystal anisotropy entries.  It contains none of the method's
+arithmetic and imports neither the GPU binding nor the oracle, so that both
+can be driven from the same configuration.
+
+The paper's workloads are themselves synthetic (diffuse seeds in a box,
+Sec. 2 Eq. Initial_Condition, and the set-ups of Sec. 3.4, 4.2, 4.3 and 5).
+The presets below follow the five benchmark configurations of this project:
+
+* ``c0``  128^2 D2Q9/D2Q5, periodic, one seed R = 10, four-fold a_s, 2000 steps.
+* ``c1``  2048^2, 20 seeds R = 5 at seeded random positions, per-crystal
+  four-fold a_s rotated by theta0_k, crystal index field, zero flux.
+* ``c2``  256^3 D3Q19/D3Q7, cubic a_s (Eq. As_Function_Classical), zero flux.
+* ``c3``  512^3 D3Q19/D3Q7, Hoyt-Asta-Karma a_s (Eq. As_MatSci), zero flux.
+* ``c4``  256 independent 2D simulations of seeded uneven sizes and parameters.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from dataclasses import dataclass, field
+from typing import List, Tuple
+
+import numpy as np
+
+LATTICES = ("D2Q9_D2Q5", "D3Q19_D3Q7")
+BOUNDARIES = ("periodic", "zero_flux")
+GRADIENTS = ("dd", "cd")
+STORAGES = ("fp64", "fp32", "fp16")
+ANISO_KINDS = ("iso", "sectoral", "cubic", "cubic_hak")
+
+
+@dataclass
+class Aniso:
+    """One anisotropy entry (Sec. 4.1).
+
+    kind ``sectoral``: 1 + eps Re[((n_x + i n_y) e^{-i phi0})^q] (Eq. As_Theta,
+    Eq. As_Multi; Eq. As_Y66 in 3D with q = 6).  ``cubic``: Eq.
+    As_Function_Classical.  ``cubic_hak``: Eq. As_MatSci with (eps, gamma).
+    """
+
+    kind: str = "iso"
+    eps: float = 0.0
+    q: int = 4
+    phi0: float = 0.0
+    gamma: float = 0.0
+
+
+@dataclass
+class Seed:
+    """A diffuse seed (Eq. Initial_Condition); centre and radius in lattice units."""
+
+    x: float
+    y: float
+    z: float = 0.0
+    radius: float = 10.0
+    id: int = 1
+
+
+@dataclass
+class SimConfig:
+    lattice: str = "D2Q9_D2Q5"
+    nx: int = 128
+    ny: int = 128
+    nz: int = 1
+    boundary: str = "periodic"
+    gradient: str = "dd"
+    storage: str = "fp64"
+    W0: float = 1.0
+    tau0: float = 1.0
+    lam: float = 10.0
+    kappa: float = 6.267
+    delta: float = 0.3
+    dx: float = 0.4
+    dt: float = 0.008
+    xi: float = 1e-7
+    aniso: List[Aniso] = field(default_factory=lambda: [Aniso("sectoral", 0.05, 4, 0.0)])
+    seeds: List[Seed] = field(default_factory=list)
+    use_ids: bool = False
+    tip_dir: Tuple[int, int, int] = (1, 0, 0)
+
+    @property
+    def dim(self) -> int:
+        return 2 if self.lattice == "D2Q9_D2Q5" else 3
+
+    @property
+    def nodes(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def shape(self) -> Tuple[int, ...]:
+        """numpy shape of a field, slowest axis first: (ny, nx) or (nz, ny, nx)."""
+        return (self.ny, self.nx) if self.dim == 2 else (self.nz, self.ny, self.nx)
+
+    def replace(self, **kw) -> "SimConfig":
+        return dataclasses.replace(self, **kw)
+
+    def validate(self) -> None:
+        assert self.lattice in LATTICES, self.lattice
+        assert self.boundary in BOUNDARIES, self.boundary
+        assert self.gradient in GRADIENTS, self.gradient
+        assert self.storage in STORAGES, self.storage
+        for a in self.aniso:
+            assert a.kind in ANISO_KINDS, a.kind
+        if self.dim == 2:
+            assert self.nz == 1
+
+
+# ----------------------------------------------------------------------------
+# Presets.  Unstated parameters follow the paper's Sec. 3.4 set-up:
+# W0 = tau0 = 1, dx = 0.4, dt = 0.008, lambda = 10, kappa = D = 0.6267 lambda.
+# ----------------------------------------------------------------------------
+KAPPA_C0 = 0.6267 * 10.0
+
+
+def c0(storage: str = "fp64", gradient: str = "dd", n: int = 128) -> SimConfig:
+    """128^2, periodic, one centred seed R = 10 lu, a_s = 1 + 0.05 cos 4 phi."""
+    c = n // 2
+    return SimConfig(
+        lattice="D2Q9_D2Q5", nx=n, ny=n, nz=1, boundary="periodic", gradient=gradient,
+        storage=storage, delta=0.3, kappa=KAPPA_C0,
+        aniso=[Aniso("sectoral", eps=0.05, q=4, phi0=0.0)],
+        seeds=[Seed(c, c, 0.0, 10.0, 1)], tip_dir=(1, 0, 0))
+
+
+C0_STEPS = 2000
+
+
+def c1_seeds(n: int = 2048, count: int = 20, radius: float = 5.0, margin: int = 32,
+             min_gap: float = 32.0, rng_seed: int = 160601):
+    """Seed centres ~ U[margin, n - margin)^2 with pairwise distance >= min_gap,
+    and per-crystal orientation theta0 ~ U[0, pi/2)."""
+    rng = np.random.default_rng(rng_seed)
+    pts: List[Tuple[float, float]] = []
+    while len(pts) < count:
+        p = rng.integers(margin, n - margin, size=2)
+        if all(math.hypot(p[0] - q[0], p[1] - q[1]) >= min_gap for q in pts):
+            pts.append((int(p[0]), int(p[1])))
+    theta = rng.uniform(0.0, math.pi / 2, size=count)
+    return pts, [float(t) for t in theta]
+
+
+def c1(storage: str = "fp64", gradient: str = "dd", n: int = 2048, count: int = 20,
+       rng_seed: int = 160601) -> SimConfig:
+    pts, theta = c1_seeds(n, count, rng_seed=rng_seed,
+                          margin=max(4, min(32, n // 16)), min_gap=max(8.0, min(32.0, n / 8)))
+    aniso = [Aniso("iso")] + [Aniso("sectoral", eps=0.05, q=4, phi0=t) for t in theta]
+    seeds = [Seed(px, py, 0.0, 5.0, k + 1) for k, (px, py) in enumerate(pts)]
+    return SimConfig(
+        lattice="D2Q9_D2Q5", nx=n, ny=n, nz=1, boundary="zero_flux", gradient=gradient,
+        storage=storage, delta=0.5, kappa=KAPPA_C0, aniso=aniso, seeds=seeds, use_ids=True,
+        tip_dir=(1, 0, 0))
+
+
+C1_STEPS = 20000
+
+
+def c2(storage: str = "fp64", n: int = 256, radius: float = 8.0) -> SimConfig:
+    c = n // 2
+    return SimConfig(
+        lattice="D3Q19_D3Q7", nx=n, ny=n, nz=n, boundary="zero_flux", gradient="dd",
+        storage=storage, delta=0.55, kappa=KAPPA_C0, aniso=[Aniso("cubic", eps=0.05)],
+        seeds=[Seed(c, c, c, radius, 1)], tip_dir=(1, 0, 0))
+
+
+C2_STEPS = 10000
+
+# (eps_1, eps_2) of Eq. As_MatSci for the three 512^3 runs, with the lattice
+# direction of the favoured growth used as the tip ray.
+C3_VARIANTS = {
+    "100": ((0.1, 0.0), (1, 0, 0)),
+    "111": ((-0.02, 0.0), (1, 1, 1)),
+    "110": ((0.0, -0.05), (1, 1, 0)),
+}
+
+
+def c3(storage: str = "fp16", variant: str = "100", n: int = 512, radius: float = 8.0) -> SimConfig:
+    (e1, e2), tip = C3_VARIANTS[variant]
+    c = n // 2
+    return SimConfig(
+        lattice="D3Q19_D3Q7", nx=n, ny=n, nz=n, boundary="zero_flux", gradient="dd",
+        storage=storage, delta=0.6, kappa=KAPPA_C0,
+        aniso=[Aniso("cubic_hak", eps=e1, gamma=e2)],
+        seeds=[Seed(c, c, c, radius, 1)], tip_dir=tip)
+
+
+C3_STEPS = 20000
+
+
+def c4(count: int = 256, rng_seed: int = 160604, storage: str = "fp32",
+       side_lo: int = 2, side_hi: int = 16) -> List[SimConfig]:
+    """Ensemble of independent 2D simulations with seeded uneven sizes/parameters."""
+    rng = np.random.default_rng(rng_seed)
+    out = []
+    for _ in range(count):
+        nx = 32 * int(rng.integers(side_lo, side_hi + 1))
+        ny = 32 * int(rng.integers(side_lo, side_hi + 1))
+        eps = float(rng.uniform(0.01, 0.07))
+        delta = float(rng.uniform(0.2, 0.6))
+        radius = float(rng.uniform(4.0, 12.0))
+        out.append(SimConfig(
+            lattice="D2Q9_D2Q5", nx=nx, ny=ny, nz=1, boundary="zero_flux", gradient="dd",
+            storage=storage, delta=delta, kappa=KAPPA_C0,
+            aniso=[Aniso("sectoral", eps=eps, q=4, phi0=0.0)],
+            seeds=[Seed(nx // 2, ny // 2, 0.0, radius, 1)], tip_dir=(1, 0, 0)))
+    return out
+
+
+C4_STEPS = 5000
+
+
+def small_3d(storage: str = "fp64", n: int = 48, aniso: Aniso | None = None,
+             boundary: str = "zero_flux", radius: float = 6.0, delta: float = 0.55,
+             nx: int | None = None, ny: int | None = None, nz: int | None = None) -> SimConfig:
+    """A short 3D case the oracle finishes in seconds (parity tests)."""
+    nx = nx or n
+    ny = ny or n
+    nz = nz or n
+    return SimConfig(
+        lattice="D3Q19_D3Q7", nx=nx, ny=ny, nz=nz, boundary=boundary, gradient="dd",
+        storage=storage, delta=delta, kappa=KAPPA_C0,
+        aniso=[aniso or Aniso("cubic", eps=0.05)],
+        seeds=[Seed(nx // 2, ny // 2, nz // 2, radius, 1)], tip_dir=(1, 0, 0))
