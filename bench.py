@@ -1,0 +1,164 @@
+"""Benchmark of the coupled LB phase-field step on one MI355X.
+
+Workload: D3Q19 (phi) + D3Q7 (u), 512^3 nodes, zero-flux walls, one central
+seed of radius 8, the Hoyt-Asta-Karma anisotropy (Eq. As_MatSci) with
+(eps1, eps2) = (0.1, 0), undercooling 0.6.  A step is one pass of the whole
+hot path (gradient, a_s / N, the nonlocal phase-field LBE, bounce-back, the
+heat LBE) over the full grid, one fused kernel launch.
+
+The JSON line reports the FP16-offset storage form (FP32 arithmetic) as the
+headline `value` and the plain FP64 form beside it, both in MLUPS (million
+node updates per second), each with its HBM roofline; plus the CPU FP64
+oracle timed on a bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "coupled φ+u MLUPS & %HBM roofline, D3Q19 512³, FP64 vs FP16-offset storage"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per node-step: every distribution read once and written
+# once; offset forms also read and write the FP32 phi and u* fields.
+B_ALG = {("D3Q19_D3Q7", "fp64"): 416, ("D3Q19_D3Q7", "fp32"): 224, ("D3Q19_D3Q7", "fp16"): 120,
+         ("D2Q9_D2Q5", "fp64"): 224, ("D2Q9_D2Q5", "fp32"): 128, ("D2Q9_D2Q5", "fp16"): 72}
+KERNEL_SOURCES = ["paper_1606_09432_amd/csrc/lbpf_step.hip", "paper_1606_09432_amd/csrc/lbpf_common.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, p), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    ent = d.get("kernels", {}).get(storage)
+    if not ent or ent.get("kernel_sha") != kernel_sha():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def run_gpu(cfg, steps: int, warmup: int, autotune: bool):
+    import torch
+
+    import paper_1606_09432_amd as lb
+
+    print(f"[bench] {cfg.storage}: init {cfg.nx}x{cfg.ny}x{cfg.nz}", file=sys.stderr, flush=True)
+    sim = lb.Simulation(cfg)
+    if autotune:
+        sim.autotune(2)
+    stream = torch.cuda.current_stream()
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    diag = sim.diagnostics()[0]
+    tile = sim.get_tile()
+    del sim
+    torch.cuda.empty_cache()
+    nodes = cfg.nodes
+    mlups = nodes * steps / (ms * 1e-3) / 1e6
+    b_alg = B_ALG[(cfg.lattice, cfg.storage)]
+    achieved = b_alg * nodes / (ms / steps * 1e-3) / 1e9
+    traffic = measured_traffic(cfg.storage)
+    print(f"[bench] {cfg.storage}: {ms / steps:.3f} ms/step  {mlups:.1f} MLUPS  {achieved:.0f} GB/s "
+          f"tile={tile} tip={diag['tip_position']:.3f}", file=sys.stderr, flush=True)
+    return {
+        "value": mlups, "ms_per_step": ms / steps, "tile": list(tile),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "bytes_per_node_step": b_alg},
+        "diag": {"tip_position": diag["tip_position"], "solid_fraction": diag["solid_fraction"],
+                 "nonfinite": diag["nonfinite"]},
+    }
+
+
+def cpu_baseline(cfg_full, sample_n: int, sample_steps: int):
+    """The CPU FP64 oracle on a bounded sample: the same parameters on a
+    sample_n^3 box around the seed, sample_steps steps."""
+    from oracle import oracle as O
+
+    c = sample_n // 2
+    cfg = cfg_full.replace(nx=sample_n, ny=sample_n, nz=sample_n, storage="fp64")
+    cfg.seeds = [type(cfg_full.seeds[0])(c, c, c, cfg_full.seeds[0].radius, 1)]
+    sim = O.OracleSim(cfg)
+    sim.step(1)
+    t0 = time.perf_counter()
+    sim.step(sample_steps)
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": cfg.nodes * sample_steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{sample_n}^3 box of the same workload (seed centred), {sample_steps} FP64 steps, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=512, help="grid side (the workload is 512)")
+    ap.add_argument("--variant", default="100", choices=["100", "111", "110"])
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=96)
+    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--only", choices=["fp16", "fp64", "fp32"], default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the z-slab sharding is a "
+              "design note only); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_1606_09432_amd import workloads as W
+
+    results = {}
+    storages = [args.only] if args.only else ["fp16", "fp64"]
+    for st in storages:
+        results[st] = run_gpu(W.c3(st, args.variant, n=args.n), args.steps, args.warmup, args.autotune)
+    head = "fp16" if "fp16" in results else storages[0]
+    r = results[head]
+    out = {
+        "metric": METRIC, "value": r["value"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32" if head != "fp64" else "f64", "data": "synthetic",
+        "config": {"workload": f"D3Q19 phi + D3Q7 u, {args.n}^3, zero-flux, one central seed R=8, "
+                               f"Eq. As_MatSci variant <{args.variant}>, Delta=0.6, "
+                               f"{'FP16-offset storage' if head == 'fp16' else head} (headline)",
+                   "grid": [args.n] * 3, "storage": head, "tile_y_chunk": r["tile"]},
+        "roofline": r["roofline"],
+    }
+    for st, rr in results.items():
+        if st != head:
+            out[st] = {"value": rr["value"], "unit": "MLUPS", "ms_per_step": rr["ms_per_step"],
+                       "dtype": "f64" if st == "fp64" else "f32", "roofline": rr["roofline"], "tile_y_chunk": rr["tile"]}
+    if "fp64" in results and "fp16" in results:
+        out["fp16_over_fp64"] = results["fp16"]["value"] / results["fp64"]["value"]
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(W.c3("fp64", args.variant, n=args.n), args.cpu_sample, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,532 @@
+// C ABI of the library (include/lb_pf.h): configuration checks, lattice-unit
+// conversion, workspace layout, launches and diagnostics.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lb_pf.h"
+#include "lbpf_kernels.hpp"
+
+using namespace lbpf;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                            \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) return fail(LBPF_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+struct SimHost {
+  lbpf_config cfg;
+  std::vector<lbpf_aniso> aniso;
+  std::vector<lbpf_seed> seeds;
+  int dim = 2, storage = 0;
+  int nx = 0, nyp = 0, nm = 0, pitch = 0;
+  long long mstride = 0, fstride = 0;
+  int qp = 9, qu = 5;
+  size_t dsz = 8, psz = 8;
+  // byte offsets inside the workspace
+  size_t state_off[2] = {0, 0};
+  size_t state_bytes = 0;
+  size_t off_g = 0, off_f = 0, off_phi = 0, off_us = 0, off_id = 0;  // inside a state block
+  size_t off_aniso = 0, off_seeds = 0, off_part = 0, off_res = 0;
+  double kphi = 0, s = 0, omega_u = 0, width = 0;
+  TileDev tile{};
+};
+
+}  // namespace
+
+struct lbpf_handle {
+  std::vector<SimHost> sims;
+  char *ws = nullptr;
+  size_t bytes = 0;
+  int parity = 0;
+  int64_t step = 0;
+};
+
+namespace {
+
+int validate(const lbpf_config &c) {
+  if (c.lattice != LBPF_D2Q9_D2Q5 && c.lattice != LBPF_D3Q19_D3Q7) return fail(LBPF_ERR_ARG, "unknown lattice");
+  const int dim = c.lattice == LBPF_D2Q9_D2Q5 ? 2 : 3;
+  if (c.nx < 3 || c.ny < 3) return fail(LBPF_ERR_ARG, "nx and ny must be >= 3");
+  if (dim == 2 && c.nz != 1) return fail(LBPF_ERR_ARG, "nz must be 1 for the 2D lattice pair");
+  if (dim == 3 && c.nz < 3) return fail(LBPF_ERR_ARG, "nz must be >= 3 in 3D");
+  if ((long long)c.nx * c.ny * c.nz > (1LL << 31) * 4) return fail(LBPF_ERR_ARG, "grid too large");
+  if (c.boundary != LBPF_PERIODIC && c.boundary != LBPF_ZERO_FLUX) return fail(LBPF_ERR_ARG, "unknown boundary");
+  if (c.gradient != LBPF_GRAD_DD && c.gradient != LBPF_GRAD_CD) return fail(LBPF_ERR_ARG, "unknown gradient");
+  if (c.storage < LBPF_FP64 || c.storage > LBPF_FP16_OFFSET) return fail(LBPF_ERR_ARG, "unknown storage");
+  if (!(c.W0 > 0) || !(c.tau0 > 0) || !(c.dx > 0) || !(c.kappa > 0) || !std::isfinite(c.lambda) ||
+      !std::isfinite(c.delta) || !(c.xi >= 0))
+    return fail(LBPF_ERR_ARG, "W0, tau0, dx, kappa must be > 0 and lambda, delta, xi finite");
+  if (!(c.dt > 0)) return fail(LBPF_ERR_UNSTABLE, "dt must be > 0");
+  if (c.n_aniso < 1 || c.n_aniso > kMaxAniso || !c.aniso) return fail(LBPF_ERR_ARG, "need 1..256 anisotropy entries");
+  for (int k = 0; k < c.n_aniso; ++k) {
+    const lbpf_aniso &a = c.aniso[k];
+    if (a.kind < LBPF_ANISO_ISO || a.kind > LBPF_ANISO_CUBIC_HAK) return fail(LBPF_ERR_ARG, "unknown anisotropy kind");
+    if (a.kind == LBPF_ANISO_SECTORAL && (a.q < 1 || a.q > 64)) return fail(LBPF_ERR_ARG, "sectoral q must be 1..64");
+    if (!std::isfinite(a.eps) || !std::isfinite(a.gamma) || !std::isfinite(a.phi0))
+      return fail(LBPF_ERR_ARG, "anisotropy parameters must be finite");
+  }
+  if (c.use_ids && c.aniso[0].kind != LBPF_ANISO_ISO)
+    return fail(LBPF_ERR_ARG, "with the index field, entry 0 must be isotropic");
+  if (c.n_seeds < 0 || (c.n_seeds > 0 && !c.seeds)) return fail(LBPF_ERR_ARG, "bad seed list");
+  for (int k = 0; k < c.n_seeds; ++k) {
+    const lbpf_seed &s = c.seeds[k];
+    if (s.crystal_id < 0 || (c.use_ids && s.crystal_id >= c.n_aniso))
+      return fail(LBPF_ERR_ARG, "seed crystal id out of range");
+    if (!std::isfinite(s.x) || !std::isfinite(s.y) || !std::isfinite(s.z) || !std::isfinite(s.radius))
+      return fail(LBPF_ERR_ARG, "seed must be finite");
+  }
+  return LBPF_OK;
+}
+
+// Lattice-unit numbers (Eq. ThermalDiffusivity, Eq. LBE_RelaxationTime):
+// Dphi = W0^2 dt/(tau0 dx^2), s = dt/tau0, Du = kappa dt/dx^2, eta_u = Du/e^2 + 1/2.
+void units(const lbpf_config &c, SimHost &s) {
+  const double inv_e2_p = 3.0;
+  const double inv_e2_u = s.dim == 2 ? 3.0 : 4.0;
+  const double Dphi = c.W0 * c.W0 * c.dt / (c.tau0 * c.dx * c.dx);
+  const double Du = c.kappa * c.dt / (c.dx * c.dx);
+  s.kphi = Dphi * inv_e2_p;
+  s.s = c.dt / c.tau0;
+  s.omega_u = 1.0 / (Du * inv_e2_u + 0.5);
+  s.width = std::sqrt(2.0) * (c.W0 / c.dx);
+}
+
+void default_tile(SimHost &s) {
+  TileDev &t = s.tile;
+  t.ty = s.dim == 3 ? (s.storage == LBPF_FP64 ? 4 : 4) : 1;
+  t.tiles_x = (s.nx + 63) / 64;
+  t.tiles_y = s.dim == 3 ? (s.nyp + t.ty - 1) / t.ty : 1;
+  const long long tiles = (long long)t.tiles_x * t.tiles_y;
+  const long long target = 8192;
+  long long ch = (s.nm * tiles + target - 1) / target;
+  ch = std::max<long long>(ch, s.dim == 3 ? 16 : 16);
+  ch = std::min<long long>(ch, s.nm);
+  t.chunk = (int)ch;
+  t.nchunks = (s.nm + t.chunk - 1) / t.chunk;
+}
+
+int set_tile(SimHost &s, int ty, int chunk) {
+  TileDev t = s.tile;
+  if (ty > 0) {
+    if (s.dim == 2 && ty != 1) return fail(LBPF_ERR_UNSUPPORTED, "2D tiles are one row high");
+    if (s.dim == 3 && ty != 2 && ty != 4 && ty != 8) return fail(LBPF_ERR_UNSUPPORTED, "tile_y must be 2, 4 or 8");
+    if (s.dim == 3 && ty == 8 && s.storage == LBPF_FP64) return fail(LBPF_ERR_UNSUPPORTED, "tile_y 8 needs FP32 arithmetic");
+    t.ty = ty;
+  }
+  if (chunk > 0) t.chunk = std::min(chunk, s.nm);
+  t.tiles_x = (s.nx + 63) / 64;
+  t.tiles_y = s.dim == 3 ? (s.nyp + t.ty - 1) / t.ty : 1;
+  t.nchunks = (s.nm + t.chunk - 1) / t.chunk;
+  if ((long long)t.tiles_x * t.tiles_y * t.nchunks > 0x7fffffffLL) return fail(LBPF_ERR_ARG, "too many work-groups");
+  s.tile = t;
+  return LBPF_OK;
+}
+
+// Workspace layout of one simulation starting at `cursor`.
+void plan(const lbpf_config &c, SimHost &s, size_t &cursor) {
+  s.cfg = c;
+  s.dim = c.lattice == LBPF_D2Q9_D2Q5 ? 2 : 3;
+  s.storage = c.storage;
+  s.qp = s.dim == 2 ? 9 : 19;
+  s.qu = s.dim == 2 ? 5 : 7;
+  s.nx = c.nx;
+  s.nyp = s.dim == 3 ? c.ny : 1;
+  s.nm = s.dim == 3 ? c.nz : c.ny;
+  s.pitch = (int)align_up((size_t)c.nx, 64);
+  s.mstride = (long long)s.pitch * s.nyp;
+  s.fstride = s.mstride * s.nm;
+  s.dsz = c.storage == LBPF_FP64 ? 8 : (c.storage == LBPF_FP32_OFFSET ? 4 : 2);
+  s.psz = c.storage == LBPF_FP64 ? 8 : 4;
+  const size_t field = (size_t)s.fstride;
+  size_t o = 0;
+  s.off_g = o;
+  o = align_up(o + field * s.qp * s.dsz);
+  s.off_f = o;
+  o = align_up(o + field * s.qu * s.dsz);
+  s.off_phi = o;
+  o = align_up(o + field * s.psz);
+  s.off_us = o;
+  if (c.storage != LBPF_FP64) o = align_up(o + field * 4);
+  s.off_id = o;
+  if (c.use_ids) o = align_up(o + field * 2);
+  s.state_bytes = o;
+  cursor = align_up(cursor);
+  s.state_off[0] = cursor;
+  cursor += s.state_bytes;
+  s.state_off[1] = cursor;
+  cursor += s.state_bytes;
+  s.off_aniso = cursor;
+  cursor = align_up(cursor + sizeof(AnisoDev) * (size_t)c.n_aniso);
+  s.off_seeds = cursor;
+  cursor = align_up(cursor + sizeof(SeedDev) * (size_t)std::max(1, c.n_seeds));
+  s.off_part = cursor;
+  cursor = align_up(cursor + sizeof(double) * kDiagVals * kDiagBlocks);
+  s.off_res = cursor;
+  cursor = align_up(cursor + sizeof(double) * (kDiagVals + 2));
+}
+
+// SimDev for a step that reads buffer `in` and writes buffer 1 - in.
+SimDev make_dev(const lbpf_handle *h, const SimHost &s, int in) {
+  SimDev d{};
+  char *base = h->ws;
+  char *A = base + s.state_off[in];
+  char *B = base + s.state_off[1 - in];
+  d.nx = s.nx;
+  d.nyp = s.nyp;
+  d.nm = s.nm;
+  d.pitch = s.pitch;
+  d.mstride = s.mstride;
+  d.fstride = s.fstride;
+  d.periodic = s.cfg.boundary == LBPF_PERIODIC;
+  d.grad_cd = s.cfg.gradient == LBPF_GRAD_CD;
+  d.use_ids = s.cfg.use_ids != 0;
+  d.n_aniso = s.cfg.n_aniso;
+  d.kphi = s.kphi;
+  d.s = s.s;
+  d.lambda = s.cfg.lambda;
+  d.omega_u = s.omega_u;
+  d.xi2 = s.cfg.xi * s.cfg.xi;
+  d.width = s.width;
+  d.u0 = -s.cfg.delta;
+  d.g_in = A + s.off_g;
+  d.g_out = B + s.off_g;
+  d.f_in = A + s.off_f;
+  d.f_out = B + s.off_f;
+  d.phi_in = A + s.off_phi;
+  d.phi_out = B + s.off_phi;
+  d.us_in = s.storage == LBPF_FP64 ? nullptr : reinterpret_cast<const float *>(A + s.off_us);
+  d.us_out = s.storage == LBPF_FP64 ? nullptr : reinterpret_cast<float *>(B + s.off_us);
+  d.id_in = s.cfg.use_ids ? reinterpret_cast<const int16_t *>(A + s.off_id) : nullptr;
+  d.id_out = s.cfg.use_ids ? reinterpret_cast<int16_t *>(B + s.off_id) : nullptr;
+  d.aniso = reinterpret_cast<const AnisoDev *>(base + s.off_aniso);
+  return d;
+}
+
+// A SimDev whose *_out pointers address the current state (for init/import).
+SimDev make_dev_current(const lbpf_handle *h, const SimHost &s) {
+  SimDev d = make_dev(h, s, 1 - h->parity);
+  return d;
+}
+
+int check_sim(const lbpf_handle *h, int sim) {
+  if (!h) return fail(LBPF_ERR_ARG, "null handle");
+  if (sim < 0 || sim >= (int)h->sims.size()) return fail(LBPF_ERR_ARG, "simulation index out of range");
+  return LBPF_OK;
+}
+
+int plan_all(const lbpf_config *cfgs, int n_sims, std::vector<SimHost> &sims, size_t &total) {
+  if (!cfgs || n_sims < 1) return fail(LBPF_ERR_ARG, "need at least one config");
+  sims.assign(n_sims, SimHost());
+  size_t cursor = 0;
+  for (int k = 0; k < n_sims; ++k) {
+    int rc = validate(cfgs[k]);
+    if (rc) return rc;
+    if (n_sims > 1 && (cfgs[k].lattice != LBPF_D2Q9_D2Q5 || cfgs[k].lattice != cfgs[0].lattice ||
+                       cfgs[k].storage != cfgs[0].storage))
+      return fail(LBPF_ERR_UNSUPPORTED, "a batched ensemble must be 2D with one storage mode");
+    plan(cfgs[k], sims[k], cursor);
+    sims[k].aniso.assign(cfgs[k].aniso, cfgs[k].aniso + cfgs[k].n_aniso);
+    sims[k].seeds.assign(cfgs[k].seeds, cfgs[k].seeds + cfgs[k].n_seeds);
+    sims[k].cfg.aniso = sims[k].aniso.data();
+    sims[k].cfg.seeds = sims[k].seeds.data();
+    units(cfgs[k], sims[k]);
+    default_tile(sims[k]);
+  }
+  total = align_up(cursor);
+  return LBPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lb_pf_last_error(void) { return g_last_error.c_str(); }
+
+int lb_pf_sharp_interface(double W0, double tau0, double lambda, double kappa, double *d0, double *beta,
+                          double *lambda_star) {
+  if (!(W0 > 0) || !(tau0 > 0) || !(kappa > 0) || !(lambda != 0)) return fail(LBPF_ERR_ARG, "bad parameters");
+  const double a1 = 5.0 * std::sqrt(2.0) / 8.0, a2 = 0.6267;
+  if (d0) *d0 = a1 * W0 / lambda;
+  if (beta) *beta = a1 * (tau0 / (W0 * lambda) - a2 * W0 / kappa);
+  if (lambda_star) *lambda_star = kappa * tau0 / (a2 * W0 * W0);
+  return LBPF_OK;
+}
+
+int lb_pf_workspace_bytes(const lbpf_config *cfgs, int n_sims, size_t *bytes) {
+  if (!bytes) return fail(LBPF_ERR_ARG, "bytes is NULL");
+  std::vector<SimHost> sims;
+  size_t total = 0;
+  int rc = plan_all(cfgs, n_sims, sims, total);
+  if (rc) return rc;
+  *bytes = total;
+  return LBPF_OK;
+}
+
+int lb_pf_init(const lbpf_config *cfgs, int n_sims, void *dev_workspace, size_t bytes, void *hip_stream,
+               lbpf_handle **out) {
+  if (!out) return fail(LBPF_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  lbpf_handle *h = new lbpf_handle();
+  size_t total = 0;
+  int rc = plan_all(cfgs, n_sims, h->sims, total);
+  if (rc) {
+    delete h;
+    return rc;
+  }
+  if (!dev_workspace || (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) != 0 || bytes < total) {
+    delete h;
+    return fail(LBPF_ERR_WORKSPACE, "workspace NULL, not 256-byte aligned, or smaller than lb_pf_workspace_bytes()");
+  }
+  h->ws = static_cast<char *>(dev_workspace);
+  h->bytes = bytes;
+  h->parity = 0;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (SimHost &s : h->sims) {
+    std::vector<AnisoDev> tab(s.cfg.n_aniso);
+    for (int k = 0; k < s.cfg.n_aniso; ++k) {
+      const lbpf_aniso &a = s.aniso[k];
+      tab[k].kind = a.kind;
+      tab[k].q = a.q;
+      tab[k].eps = a.eps;
+      tab[k].gamma = a.gamma;
+      tab[k].cr = std::cos(a.q * a.phi0);
+      tab[k].ci = -std::sin(a.q * a.phi0);
+    }
+    std::vector<SeedDev> sd(std::max(1, s.cfg.n_seeds));
+    for (int k = 0; k < s.cfg.n_seeds; ++k) {
+      sd[k] = SeedDev{s.seeds[k].x, s.seeds[k].y, s.seeds[k].z, s.seeds[k].radius, s.seeds[k].crystal_id};
+    }
+    hipError_t e = hipMemcpyAsync(h->ws + s.off_aniso, tab.data(), sizeof(AnisoDev) * tab.size(),
+                                  hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->ws + s.off_seeds, sd.data(), sizeof(SeedDev) * sd.size(), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+      SimDev d = make_dev_current(h, s);
+      InitSrc src{};
+      src.seeds = reinterpret_cast<const SeedDev *>(h->ws + s.off_seeds);
+      src.n_seeds = s.cfg.n_seeds;
+      src.nx = s.cfg.nx;
+      src.ny = s.cfg.ny;
+      e = launch_init(s.dim, s.storage, d, d.id_out, src, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      delete h;
+      return fail(LBPF_ERR_HIP, std::string("initialisation failed: ") + hipGetErrorString(e));
+    }
+  }
+  *out = h;
+  return LBPF_OK;
+}
+
+int lb_pf_step(lbpf_handle *h, int n_steps, void *hip_stream) {
+  if (!h) return fail(LBPF_ERR_ARG, "null handle");
+  if (n_steps < 0) return fail(LBPF_ERR_ARG, "n_steps < 0");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  for (int n = 0; n < n_steps; ++n) {
+    for (const SimHost &s : h->sims) {
+      const SimDev d = make_dev(h, s, h->parity);
+      HIPCHK(launch_step(s.dim, s.storage, d, s.tile, st));
+    }
+    h->parity ^= 1;
+    h->step++;
+  }
+  return LBPF_OK;
+}
+
+int lb_pf_diagnostics(lbpf_handle *h, lbpf_diag *out, void *hip_stream) {
+  if (!h || !out) return fail(LBPF_ERR_ARG, "null argument");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  int bad = 0;
+  for (size_t k = 0; k < h->sims.size(); ++k) {
+    const SimHost &s = h->sims[k];
+    const SimDev d = make_dev(h, s, h->parity);
+    int dir[3] = {s.cfg.tip_dir[0], s.cfg.tip_dir[1], s.cfg.tip_dir[2]};
+    if (!dir[0] && !dir[1] && !dir[2]) dir[0] = 1;
+    int o[3] = {s.cfg.nx / 2, s.cfg.ny / 2, s.cfg.nz / 2};
+    if (s.cfg.n_seeds > 0) {
+      o[0] = (int)std::floor(s.seeds[0].x + 0.5);
+      o[1] = (int)std::floor(s.seeds[0].y + 0.5);
+      o[2] = (int)std::floor(s.seeds[0].z + 0.5);
+    }
+    double *part = reinterpret_cast<double *>(h->ws + s.off_part);
+    double *res = reinterpret_cast<double *>(h->ws + s.off_res);
+    HIPCHK(launch_diag(s.dim, s.storage, d, part, res, 0, o[0], o[1], o[2], dir[0], dir[1], dir[2], st));
+    double host[kDiagVals + 1];
+    HIPCHK(hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const double N = (double)s.cfg.nx * s.cfg.ny * s.cfg.nz;
+    lbpf_diag &r = out[k];
+    r.step = h->step;
+    r.sum_phi = host[0];
+    r.sum_u = host[1];
+    r.sum_u_minus_half_phi = host[2];
+    r.solid_fraction = host[3] / (2.0 * N);
+    r.n_solid = host[4];
+    r.nonfinite = host[5] != 0.0;
+    r.tip_position = host[kDiagVals];
+    bad |= r.nonfinite;
+  }
+  if (bad) return fail(LBPF_ERR_NONFINITE, "non-finite phi or u");
+  return LBPF_OK;
+}
+
+int lb_pf_export_fields(lbpf_handle *h, int sim, double *phi_dev, double *u_dev, int16_t *ids_dev,
+                        void *hip_stream) {
+  int rc = check_sim(h, sim);
+  if (rc) return rc;
+  const SimHost &s = h->sims[sim];
+  HIPCHK(launch_export(s.dim, s.storage, make_dev(h, s, h->parity), phi_dev, u_dev, ids_dev, nullptr, nullptr,
+                       s.cfg.ny, static_cast<hipStream_t>(hip_stream)));
+  return LBPF_OK;
+}
+
+int lb_pf_export_dists(lbpf_handle *h, int sim, double *g_dev, double *f_dev, void *hip_stream) {
+  int rc = check_sim(h, sim);
+  if (rc) return rc;
+  const SimHost &s = h->sims[sim];
+  HIPCHK(launch_export(s.dim, s.storage, make_dev(h, s, h->parity), nullptr, nullptr, nullptr, g_dev, f_dev,
+                       s.cfg.ny, static_cast<hipStream_t>(hip_stream)));
+  return LBPF_OK;
+}
+
+int lb_pf_import_fields(lbpf_handle *h, int sim, const double *phi_dev, const double *u_dev,
+                        const int16_t *ids_dev, void *hip_stream) {
+  int rc = check_sim(h, sim);
+  if (rc) return rc;
+  if (!phi_dev || !u_dev) return fail(LBPF_ERR_ARG, "phi and u are required");
+  const SimHost &s = h->sims[sim];
+  SimDev d = make_dev_current(h, s);
+  InitSrc src{};
+  src.phi = phi_dev;
+  src.u = u_dev;
+  src.ids = ids_dev;
+  src.nx = s.cfg.nx;
+  src.ny = s.cfg.ny;
+  HIPCHK(launch_init(s.dim, s.storage, d, d.id_out, src, static_cast<hipStream_t>(hip_stream)));
+  return LBPF_OK;
+}
+
+int lb_pf_state_bytes(const lbpf_handle *h, size_t *bytes) {
+  if (!h || !bytes) return fail(LBPF_ERR_ARG, "null argument");
+  size_t b = 0;
+  for (const SimHost &s : h->sims) b += s.state_bytes;
+  *bytes = b;
+  return LBPF_OK;
+}
+
+int lb_pf_save_state(lbpf_handle *h, void *dev_buf, size_t bytes, void *hip_stream) {
+  size_t need = 0;
+  int rc = lb_pf_state_bytes(h, &need);
+  if (rc) return rc;
+  if (!dev_buf || bytes < need) return fail(LBPF_ERR_ARG, "state buffer too small");
+  char *dst = static_cast<char *>(dev_buf);
+  for (const SimHost &s : h->sims) {
+    HIPCHK(hipMemcpyAsync(dst, h->ws + s.state_off[h->parity], s.state_bytes, hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(hip_stream)));
+    dst += s.state_bytes;
+  }
+  return LBPF_OK;
+}
+
+int lb_pf_load_state(lbpf_handle *h, const void *dev_buf, size_t bytes, void *hip_stream) {
+  size_t need = 0;
+  int rc = lb_pf_state_bytes(h, &need);
+  if (rc) return rc;
+  if (!dev_buf || bytes < need) return fail(LBPF_ERR_ARG, "state buffer too small");
+  const char *src = static_cast<const char *>(dev_buf);
+  for (const SimHost &s : h->sims) {
+    HIPCHK(hipMemcpyAsync(h->ws + s.state_off[h->parity], src, s.state_bytes, hipMemcpyDeviceToDevice,
+                          static_cast<hipStream_t>(hip_stream)));
+    src += s.state_bytes;
+  }
+  return LBPF_OK;
+}
+
+int lb_pf_set_tile(lbpf_handle *h, int tile_y, int chunk) {
+  if (!h) return fail(LBPF_ERR_ARG, "null handle");
+  for (SimHost &s : h->sims) {
+    int rc = set_tile(s, tile_y, chunk);
+    if (rc) return rc;
+  }
+  return LBPF_OK;
+}
+
+int lb_pf_get_tile(const lbpf_handle *h, int *tile_y, int *chunk) {
+  if (!h) return fail(LBPF_ERR_ARG, "null handle");
+  if (tile_y) *tile_y = h->sims[0].tile.ty;
+  if (chunk) *chunk = h->sims[0].tile.chunk;
+  return LBPF_OK;
+}
+
+int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream) {
+  if (!h) return fail(LBPF_ERR_ARG, "null handle");
+  if (steps_per_trial < 1) return fail(LBPF_ERR_ARG, "steps_per_trial < 1");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const SimHost &s0 = h->sims[0];
+  std::vector<int> tys = s0.dim == 3 ? std::vector<int>{2, 4, 8} : std::vector<int>{1};
+  std::vector<int> chunks = s0.dim == 3 ? std::vector<int>{16, 32, 64, 128} : std::vector<int>{16, 32, 64, 128};
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  float best = 1e30f;
+  int bty = s0.tile.ty, bch = s0.tile.chunk;
+  for (int ty : tys) {
+    if (s0.dim == 3 && ty == 8 && s0.storage == LBPF_FP64) continue;
+    for (int ch : chunks) {
+      if (lb_pf_set_tile(h, ty, ch)) continue;
+      int rc = lb_pf_step(h, 1, hip_stream);  // warm-up
+      if (rc) return rc;
+      HIPCHK(hipEventRecord(e0, st));
+      rc = lb_pf_step(h, steps_per_trial, hip_stream);
+      if (rc) return rc;
+      HIPCHK(hipEventRecord(e1, st));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        bty = ty;
+        bch = ch;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return lb_pf_set_tile(h, bty, bch);
+}
+
+int lb_pf_info(const lbpf_handle *h, int sim, int64_t *nodes, int64_t *step, int *q_phi, int *q_u) {
+  int rc = check_sim(h, sim);
+  if (rc) return rc;
+  const SimHost &s = h->sims[sim];
+  if (nodes) *nodes = (int64_t)s.cfg.nx * s.cfg.ny * s.cfg.nz;
+  if (step) *step = h->step;
+  if (q_phi) *q_phi = s.qp;
+  if (q_u) *q_u = s.qu;
+  return LBPF_OK;
+}
+
+int lb_pf_destroy(lbpf_handle *h) {
+  delete h;
+  return LBPF_OK;
+}
+
+}  // extern "C"

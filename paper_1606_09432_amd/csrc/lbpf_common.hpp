@@ -1,0 +1,276 @@
+// Device-side building blocks of the coupled LB phase-field step for gfx950.
+//
+// Coordinates.  Every kernel works in (x, yp, m) coordinates: m is the axis a
+// work-group marches along (z in 3D, y in 2D), yp the second in-plane axis (y
+// in 3D, always 0 in 2D).  A field element (x, yp, m) lives at
+// m * mstride + yp * pitch + x, with the x pitch padded to 64 elements so
+// that every row starts on a 128-byte line.  Distributions are stored as one
+// such field per lattice direction (structure of arrays), fstride elements
+// apart.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbpf {
+
+// ---------------------------------------------------------------------------
+// Lattices (Sec. 3.3, Table Values-Lattices; D3Q19 with the standard weights
+// 1/3, 1/18, 1/36 since the paper names but does not tabulate it).
+// ---------------------------------------------------------------------------
+struct D2Q9 {
+  static constexpr int Q = 9;
+  static constexpr int E[9][3] = {{0, 0, 0}, {1, 0, 0},  {0, 1, 0},   {-1, 0, 0}, {0, -1, 0},
+                                  {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+  static constexpr double W[9] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                                  1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  static constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+  static constexpr double INV_E2 = 3.0;
+};
+struct D2Q5 {
+  static constexpr int Q = 5;
+  static constexpr int E[5][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0}};
+  static constexpr double W[5] = {1.0 / 3, 1.0 / 6, 1.0 / 6, 1.0 / 6, 1.0 / 6};
+  static constexpr int OPP[5] = {0, 3, 4, 1, 2};
+  static constexpr double INV_E2 = 3.0;
+};
+struct D3Q19 {
+  static constexpr int Q = 19;
+  static constexpr int E[19][3] = {
+      {0, 0, 0},  {1, 0, 0},  {0, 1, 0},   {-1, 0, 0}, {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+      {1, 1, 0},  {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {1, 0, 1},  {0, 1, 1},  {-1, 0, 1},
+      {0, -1, 1}, {1, 0, -1}, {0, 1, -1},  {-1, 0, -1}, {0, -1, -1}};
+  static constexpr double W[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                                   1.0 / 18, 1.0 / 18, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                                   1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+  static constexpr int OPP[19] = {0, 3, 4, 1, 2, 6, 5, 9, 10, 7, 8, 17, 18, 15, 16, 13, 14, 11, 12};
+  static constexpr double INV_E2 = 3.0;
+};
+struct D3Q7 {
+  static constexpr int Q = 7;
+  static constexpr int E[7][3] = {{0, 0, 0}, {1, 0, 0},  {0, 1, 0}, {-1, 0, 0},
+                                  {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+  static constexpr double W[7] = {1.0 / 4, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8, 1.0 / 8};
+  static constexpr int OPP[7] = {0, 3, 4, 1, 2, 6, 5};
+  static constexpr double INV_E2 = 4.0;
+};
+
+template <int DIM> struct Lat;
+template <> struct Lat<2> {
+  using P = D2Q9;
+  using U = D2Q5;
+};
+template <> struct Lat<3> {
+  using P = D3Q19;
+  using U = D3Q7;
+};
+
+// Components of direction i along (x, yp, m).
+template <class L, int DIM> __device__ __forceinline__ constexpr int ex(int i) { return L::E[i][0]; }
+template <class L, int DIM> __device__ __forceinline__ constexpr int ey(int i) {
+  return DIM == 3 ? L::E[i][1] : 0;
+}
+template <class L, int DIM> __device__ __forceinline__ constexpr int em(int i) {
+  return DIM == 3 ? L::E[i][2] : L::E[i][1];
+}
+
+// ---------------------------------------------------------------------------
+// Storage: FP64 distributions, or FP32 arithmetic on offsets stored in FP32/FP16.
+// ---------------------------------------------------------------------------
+struct StF64 {
+  using T = double;  // arithmetic
+  using S = double;  // stored distribution
+  using P = double;  // stored phi
+  static constexpr bool OFF = false;
+  static __device__ __forceinline__ T ld(const S *p) { return *p; }
+  static __device__ __forceinline__ void st(S *p, T v) { *p = v; }
+};
+struct StF32 {
+  using T = float;
+  using S = float;
+  using P = float;
+  static constexpr bool OFF = true;
+  static __device__ __forceinline__ T ld(const S *p) { return *p; }
+  static __device__ __forceinline__ void st(S *p, T v) { *p = v; }
+};
+struct StF16 {
+  using T = float;
+  using S = __half;
+  using P = float;
+  static constexpr bool OFF = true;
+  static __device__ __forceinline__ T ld(const S *p) { return __half2float(*p); }
+  static __device__ __forceinline__ void st(S *p, T v) { *p = __float2half_rn(v); }
+};
+
+// Anisotropy entry as the kernels see it (cos/sin of q phi0 precomputed on the host).
+struct AnisoDev {
+  int kind;
+  int q;
+  double eps, gamma, cr, ci;
+};
+constexpr int kMaxAniso = 256;
+
+enum { K_ISO = 0, K_SECTORAL = 1, K_CUBIC = 2, K_CUBIC_HAK = 3 };
+
+// Everything a kernel needs to know about one simulation and one A->B step.
+struct SimDev {
+  int nx, nyp, nm, pitch;  // extents in (x, yp, m), x pitch in elements
+  long long mstride;       // elements between consecutive m planes
+  long long fstride;       // elements between consecutive distribution fields
+  int periodic, grad_cd, use_ids, n_aniso;
+  double kphi;     // Dphi / e^2 of the phi lattice
+  double s;        // dt / tau0
+  double lambda;   // coupling
+  double omega_u;  // 1 / eta_u
+  double xi2;      // xi^2 (index threshold on |p|^2)
+  double width;    // sqrt(2) W0 / dx (seed profile width, lattice units)
+  double u0;       // -delta
+  const void *g_in;
+  void *g_out;
+  const void *f_in;
+  void *f_out;
+  const void *phi_in;
+  void *phi_out;
+  const float *us_in;
+  float *us_out;
+  const int16_t *id_in;
+  int16_t *id_out;
+  const AnisoDev *aniso;
+};
+
+__device__ __forceinline__ bool in_range(int c, int n) { return (unsigned)c < (unsigned)n; }
+
+// Ghost coordinate for reads of phi (and of the index field) around the box:
+// periodic wrap, or a mirror about the wall node (phi(-k) = phi(k)) so that
+// the normal derivative vanishes on the wall.  |offset| <= 2 beyond the box.
+__device__ __forceinline__ int ghost(int c, int n, int periodic) {
+  if (periodic) return c < 0 ? c + n : (c >= n ? c - n : c);
+  return c < 0 ? -c : (c >= n ? 2 * (n - 1) - c : c);
+}
+__device__ __forceinline__ int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
+
+__device__ __forceinline__ long long lin(const SimDev &sd, int x, int yp, int m) {
+  return (long long)m * sd.mstride + (long long)yp * sd.pitch + x;
+}
+
+// ---------------------------------------------------------------------------
+// Anisotropy functions (Sec. 4.1): value a and gradient G of the polynomial in n.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void aniso_eval(const AnisoDev &A, T nx, T ny, T nz, T &a, T &Gx, T &Gy,
+                                           T &Gz) {
+  Gx = Gy = Gz = T(0);
+  if (A.kind == K_SECTORAL) {
+    // Re[z^q c] with z = n_x + i n_y, c = e^{-i q phi0}; gradient Re[q z^{q-1} c], -Im[q z^{q-1} c].
+    T pr = T(1), pi = T(0);
+    for (int k = 1; k < A.q; ++k) {
+      const T tr = pr * nx - pi * ny;
+      const T ti = pr * ny + pi * nx;
+      pr = tr;
+      pi = ti;
+    }
+    const T cr = T(A.cr), ci = T(A.ci), eps = T(A.eps);
+    const T zr = pr * nx - pi * ny, zi = pr * ny + pi * nx;
+    a = T(1) + eps * (zr * cr - zi * ci);
+    const T qf = T(A.q);
+    Gx = eps * (qf * (pr * cr - pi * ci));
+    Gy = -(eps * (qf * (pr * ci + pi * cr)));
+    return;
+  }
+  const T x2 = nx * nx, y2 = ny * ny, z2 = nz * nz;
+  const T Q = (x2 * x2 + y2 * y2) + z2 * z2;
+  const T eps = T(A.eps);
+  if (A.kind == K_CUBIC) {
+    a = (T(1) - T(3) * eps) + T(4) * eps * Q;
+    Gx = T(16) * eps * (x2 * nx);
+    Gy = T(16) * eps * (y2 * ny);
+    Gz = T(16) * eps * (z2 * nz);
+    return;
+  }
+  if (A.kind == K_CUBIC_HAK) {
+    const T gam = T(A.gamma);
+    const T S = (x2 * y2) * z2;
+    a = T(1) + eps * (Q - T(3.0 / 5.0)) + gam * ((T(3) * Q + T(66) * S) - T(17.0 / 7.0));
+    const T dQx = T(4) * (x2 * nx), dQy = T(4) * (y2 * ny), dQz = T(4) * (z2 * nz);
+    const T dSx = T(2) * nx * (y2 * z2), dSy = T(2) * ny * (x2 * z2), dSz = T(2) * nz * (x2 * y2);
+    Gx = eps * dQx + gam * (T(3) * dQx + T(66) * dSx);
+    Gy = eps * dQy + gam * (T(3) * dQy + T(66) * dSy);
+    Gz = eps * dQz + gam * (T(3) * dQz + T(66) * dSz);
+    return;
+  }
+  a = T(1);
+}
+
+// a_s and N = -|p| a (G - n (n.G)) for the gradient p, n = -p/|p|
+// (Eqs. Def_Normal_Vector, TermesAnisotropes).  Isotropic when |p|^2 <= 1e-24.
+template <class T>
+__device__ __forceinline__ void flux(const AnisoDev *A, T px, T py, T pz, T &a, T &Nx, T &Ny, T &Nz) {
+  a = T(1);
+  Nx = Ny = Nz = T(0);
+  if (A == nullptr || A->kind == K_ISO) return;
+  const T r2 = (px * px + py * py) + pz * pz;
+  if (!(r2 > T(1e-24))) return;
+  const T r = sqrt(r2);
+  const T ir = T(1) / r;
+  const T nx = -px * ir, ny = -py * ir, nz = -pz * ir;
+  T Gx, Gy, Gz;
+  aniso_eval<T>(*A, nx, ny, nz, a, Gx, Gy, Gz);
+  const T nG = (nx * Gx + ny * Gy) + nz * Gz;
+  const T ra = r * a;
+  Nx = -ra * (Gx - nx * nG);
+  Ny = -ra * (Gy - ny * nG);
+  Nz = -ra * (Gz - nz * nG);
+}
+
+// ---------------------------------------------------------------------------
+// Heat distributions are stored post-collision at their source node
+// ("stream on read"): f_i^n(y) = f*_i(y - e_i).  With zero-flux walls an
+// unknown f_i (source outside) is the opposite population f_i'^n(y) = f*_i'(y + e_i)
+// (Eq. Bounce-Back); if that source is outside too, f*_i'(y).
+// gather_u returns u^n(y) = sum_i f_i^n(y) and the decoded populations:
+//   FP64:     fd[i] = f_i^n(y)
+//   offsets:  fd[i] = f_i^n(y) - w_i u*(y), stored f*_i = w_i u* + k_i.
+// ---------------------------------------------------------------------------
+template <int DIM, class ST>
+__device__ __forceinline__ typename ST::T gather_u(const SimDev &sd, int x, int yp, int m,
+                                                   typename ST::T (&fd)[Lat<DIM>::U::Q],
+                                                   typename ST::T &ustar_self) {
+  using T = typename ST::T;
+  using LU = typename Lat<DIM>::U;
+  const typename ST::S *F = reinterpret_cast<const typename ST::S *>(sd.f_in);
+  const long long self = lin(sd, x, yp, m);
+  T us_self = T(0);
+  if constexpr (ST::OFF) us_self = sd.us_in[self];
+  T sum = T(0);
+#pragma unroll
+  for (int i = 0; i < LU::Q; ++i) {
+    int sx = x - ex<LU, DIM>(i), sy = yp - ey<LU, DIM>(i), sm = m - em<LU, DIM>(i);
+    int d = i;
+    long long src;
+    if (sd.periodic) {
+      src = lin(sd, wrapc(sx, sd.nx), DIM == 3 ? wrapc(sy, sd.nyp) : 0, wrapc(sm, sd.nm));
+    } else if (in_range(sx, sd.nx) && (DIM == 2 || in_range(sy, sd.nyp)) && in_range(sm, sd.nm)) {
+      src = lin(sd, sx, sy, sm);
+    } else {
+      d = LU::OPP[i];
+      const int tx = x + ex<LU, DIM>(i), ty = yp + ey<LU, DIM>(i), tm = m + em<LU, DIM>(i);
+      if (in_range(tx, sd.nx) && (DIM == 2 || in_range(ty, sd.nyp)) && in_range(tm, sd.nm))
+        src = lin(sd, tx, ty, tm);
+      else
+        src = self;
+    }
+    const T kv = ST::ld(F + (long long)d * sd.fstride + src);
+    if constexpr (ST::OFF) {
+      fd[i] = T(LU::W[i]) * (sd.us_in[src] - us_self) + kv;
+    } else {
+      fd[i] = kv;
+    }
+    sum += fd[i];
+  }
+  ustar_self = us_self;
+  return ST::OFF ? us_self + sum : sum;
+}
+
+}  // namespace lbpf

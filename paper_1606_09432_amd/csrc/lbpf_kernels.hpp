@@ -1,0 +1,47 @@
+// Launchers shared between the kernel sources and the C-ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <type_traits>
+
+#include "lbpf_common.hpp"
+
+namespace lbpf {
+
+// Tiling of the step kernel: tiles_x x tiles_y tiles of 64 x ty nodes, each
+// marching `chunk` planes; nchunks = ceil(extent along m / chunk).
+struct TileDev {
+  int tiles_x, tiles_y, nchunks, chunk, ty;
+};
+
+// Seeds in lattice units, in (x, y, z) order.
+struct SeedDev {
+  double x, y, z, r;
+  int id;
+};
+
+// Where the initial fields come from: the seeds (Eq. Initial_Condition, u = -delta)
+// or caller FP64 arrays in the compact x-fastest layout.
+struct InitSrc {
+  const SeedDev *seeds;
+  int n_seeds;
+  const double *phi;   // arrays (NULL when seeded)
+  const double *u;
+  const int16_t *ids;
+  int nx, ny;          // compact layout extents (x, y)
+};
+
+// Diagnostics accumulators: sum phi, sum u, sum (u - phi/2), sum (1 + phi),
+// count phi > 0, non-finite flag, then the tip position.
+constexpr int kDiagVals = 6;
+constexpr int kDiagBlocks = 512;
+
+hipError_t launch_step(int dim, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st);
+hipError_t launch_init(int dim, int storage, const SimDev &sd, int16_t *ids_out, const InitSrc &src,
+                       hipStream_t st);
+hipError_t launch_diag(int dim, int storage, const SimDev &sd, double *partials, double *result,
+                       long long nodes, int ox, int oy, int oz, int dx, int dy, int dz, hipStream_t st);
+hipError_t launch_export(int dim, int storage, const SimDev &sd, double *phi, double *u, int16_t *ids,
+                         double *g, double *f, int ny_full, hipStream_t st);
+
+}  // namespace lbpf

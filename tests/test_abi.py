@@ -1,0 +1,116 @@
+"""The C-ABI library loads and exports every entry point include/lb_pf.h declares.
+
+Runs without a GPU: only host-side entry points are called (workspace
+planning, configuration checks and the sharp-interface helper); no kernel is
+launched.
+"""
+import ctypes as C
+import json
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_1606_09432_amd as lb
+from paper_1606_09432_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lb_pf.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(lb_pf_\w+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return lb.load_library()
+
+
+def test_header_declares_what_binding_uses():
+    assert _declared() == sorted(lb.EXPORTED_SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", lb.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (lb_pf_\w+)", out))
+    missing = set(_declared()) - exported
+    assert not missing, missing
+    for name in _declared():
+        assert hasattr(lib, name)
+
+
+def test_library_is_gfx950(lib):
+    blob = open(lb.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in blob
+
+
+def test_workspace_bytes_layout(lib):
+    cfg = W.c3("fp16")
+    b = lb.workspace_bytes(cfg)
+    n = 512**3
+    # two copies of 26 FP16 distributions + FP32 phi and u* fields
+    assert 2 * n * (26 * 2 + 8) <= b < 2 * n * (26 * 2 + 8) * 1.001 + (1 << 20)
+    b64 = lb.workspace_bytes(W.c3("fp64"))
+    assert 2 * n * (26 * 8 + 8) <= b64 < 2 * n * (26 * 8 + 8) * 1.001 + (1 << 20)
+    assert b64 < 288e9 * 0.25
+
+
+def test_workspace_pads_rows_to_64(lib):
+    a = lb.workspace_bytes(W.c0(n=100))
+    b = lb.workspace_bytes(W.c0(n=128).replace(ny=100))
+    assert a == b  # 100 -> pitch 128
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (dict(nx=2), -1), (dict(lattice="D3Q19_D3Q7", nz=1), -1), (dict(dt=0.0), -2), (dict(W0=-1.0), -1),
+    (dict(aniso=[]), -1), (dict(use_ids=True), -1),
+])
+def test_invalid_configs_rejected(lib, mutate, code):
+    cfg = W.c0(n=32).replace(**mutate)
+    keep = []
+    try:
+        s = lb._to_struct(cfg, keep)
+    except AssertionError:
+        pytest.skip("rejected by the Python-side check already")
+    b = C.c_size_t()
+    rc = lib.lb_pf_workspace_bytes(C.byref(s), 1, C.byref(b))
+    assert rc == code, lib.lb_pf_last_error()
+    assert lib.lb_pf_last_error()
+
+
+def test_init_rejects_missing_workspace(lib):
+    keep = []
+    s = lb._to_struct(W.c0(n=32), keep)
+    h = C.c_void_p()
+    rc = lib.lb_pf_init(C.byref(s), 1, None, 0, None, C.byref(h))
+    assert rc == -3 and not h.value
+    rc = lib.lb_pf_init(C.byref(s), 1, C.c_void_p(0x1001), 1 << 40, None, C.byref(h))
+    assert rc == -3  # misaligned
+
+
+def test_batched_requires_2d(lib):
+    keep = []
+    arr = (lb.LbpfConfig * 2)(lb._to_struct(W.c0(n=32), keep), lb._to_struct(W.small_3d(n=8), keep))
+    b = C.c_size_t()
+    assert lib.lb_pf_workspace_bytes(arr, 2, C.byref(b)) == -6
+
+
+def test_sharp_interface_printed_values(lib):
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_values.json")))["sharp_interface"]
+    _, _, ls = lb.sharp_interface(1.0, 1.0, 1.0, g["kappa"])
+    assert abs(ls - g["lambda_star"]) < g["printed_digits_tolerance"]
+    d0, beta, _ = lb.sharp_interface(1.0, 1.0, ls, g["kappa"])
+    assert abs(d0 - g["d0"]) < g["printed_digits_tolerance"] and abs(beta) < 1e-12
+
+
+def test_product_never_imports_oracle():
+    pkg = os.path.join(ROOT, "paper_1606_09432_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"(import\s+oracle|from\s+oracle|lbpf_oracle|orc_\w+\()", txt), f

@@ -1,0 +1,306 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Every comparison is element by element on the same seeded inputs.  FP64
+storage must match the oracle within 1e-10 max-abs on phi and u (and the
+crystal index exactly); the offset storage modes (FP32 arithmetic) are held
+to the accuracy bounds written in each test.  Each case prints its name before
+touching the GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1606_09432_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _gpu_run(lb, cfg, steps, tile=None):
+    import torch
+    sim = lb.Simulation(cfg)
+    if tile:
+        sim.set_tile(*tile)
+    sim.step(steps)
+    phi, u, ids = sim.fields()
+    torch.cuda.synchronize()
+    return sim, phi.cpu().numpy(), u.cpu().numpy(), ids.cpu().numpy()
+
+
+def _oracle_run(O, cfg, steps):
+    orc = O.OracleSim(cfg.replace(storage="fp64"))
+    orc.step(steps)
+    return orc
+
+
+def _case(cfg, steps):
+    return (f"{cfg.lattice} {cfg.nx}x{cfg.ny}x{cfg.nz} {cfg.boundary} {cfg.gradient} {cfg.storage} "
+            f"ids={cfg.use_ids} steps={steps}")
+
+
+def _compare(lb, O, cfg, steps, tol=FP64_TOL, tile=None):
+    _say(_case(cfg, steps))
+    sim, phi, u, ids = _gpu_run(lb, cfg, steps, tile)
+    orc = _oracle_run(O, cfg, steps)
+    ephi = np.abs(phi - orc.phi()).max()
+    eu = np.abs(u - orc.u()).max()
+    _say(f"  max|dphi| = {ephi:.3e}  max|du| = {eu:.3e}")
+    assert ephi <= tol and eu <= tol, (ephi, eu)
+    if cfg.use_ids:
+        assert np.array_equal(ids, orc.ids())
+    return sim, orc
+
+
+# ---------------------------------------------------------------------------
+# The 128^2 periodic four-fold case, 2000 steps, FP64: the headline parity bar.
+# ---------------------------------------------------------------------------
+def test_c0_fp64_parity(gpu, oracle_mod):
+    cfg = W.c0()
+    sim, orc = _compare(gpu, oracle_mod, cfg, W.C0_STEPS)
+    dg = sim.diagnostics()[0]
+    do = orc.diagnostics()
+    assert abs(dg["sum_phi"] - do["sum_phi"]) < 1e-8
+    assert abs(dg["sum_u_minus_half_phi"] - do["sum_u_minus_half_phi"]) < 1e-8
+    assert dg["n_solid"] == do["n_solid"]
+    assert abs(dg["tip_position"] - do["tip_position"]) < 1e-8
+    assert dg["step"] == W.C0_STEPS
+
+
+@pytest.mark.parametrize("boundary,grad,nx,ny", [
+    ("zero_flux", "dd", 70, 45), ("zero_flux", "cd", 130, 67), ("periodic", "cd", 96, 80),
+    ("periodic", "dd", 65, 130), ("zero_flux", "dd", 3, 3), ("periodic", "cd", 3, 5)])
+def test_2d_fp64_parity(gpu, oracle_mod, boundary, grad, nx, ny):
+    cfg = W.c0(gradient=grad).replace(nx=nx, ny=ny, boundary=boundary,
+                                      aniso=[W.Aniso("sectoral", 0.05, 4, math.radians(20))],
+                                      seeds=[W.Seed(nx * 0.4, ny * 0.55, 0, min(nx, ny) * 0.15 + 1, 1)])
+    _compare(gpu, oracle_mod, cfg, 300 if nx > 3 else 20)
+
+
+def test_2d_distributions_parity(gpu, oracle_mod):
+    cfg = W.c0(n=72).replace(boundary="zero_flux", seeds=[W.Seed(20, 30, 0, 6, 1)])
+    _say(_case(cfg, 50))
+    sim, _, _, _ = _gpu_run(gpu, cfg, 50)
+    g, f = sim.dists()
+    orc = _oracle_run(oracle_mod, cfg, 50)
+    assert np.abs(g.cpu().numpy() - orc.g()).max() < 1e-12
+    assert np.abs(f.cpu().numpy() - orc.f()).max() < 1e-12
+
+
+@pytest.mark.parametrize("boundary,grad,shape,entry,steps", [
+    ("zero_flux", "dd", (40, 36, 33), W.Aniso("cubic", eps=0.05), 80),
+    ("periodic", "dd", (34, 32, 30), W.Aniso("cubic_hak", eps=0.0, gamma=-0.05), 60),
+    ("zero_flux", "cd", (66, 20, 18), W.Aniso("cubic_hak", eps=0.1, gamma=0.0), 40),
+    ("zero_flux", "dd", (3, 3, 3), W.Aniso("cubic", eps=0.05), 10),
+    ("periodic", "dd", (24, 24, 24), W.Aniso("sectoral", eps=0.05, q=6, phi0=0.0), 40),
+])
+def test_3d_fp64_parity(gpu, oracle_mod, boundary, grad, shape, entry, steps):
+    nx, ny, nz = shape
+    cfg = W.small_3d(nx=nx, ny=ny, nz=nz, aniso=entry, boundary=boundary,
+                     radius=max(1.5, min(shape) * 0.2)).replace(gradient=grad)
+    cfg.seeds[0].x = nx * 0.45
+    _compare(gpu, oracle_mod, cfg, steps)
+
+
+def test_3d_distributions_parity(gpu, oracle_mod):
+    cfg = W.small_3d(nx=30, ny=28, nz=26, radius=5)
+    _say(_case(cfg, 25))
+    sim, _, _, _ = _gpu_run(gpu, cfg, 25)
+    g, f = sim.dists()
+    orc = _oracle_run(oracle_mod, cfg, 25)
+    assert np.abs(g.cpu().numpy() - orc.g()).max() < 1e-12
+    assert np.abs(f.cpu().numpy() - orc.f()).max() < 1e-12
+
+
+@pytest.mark.parametrize("grad", ["dd", "cd"])
+def test_crystal_index_parity(gpu, oracle_mod, grad):
+    cfg = W.c1(n=160, count=5, gradient=grad)
+    _compare(gpu, oracle_mod, cfg, 300)
+
+
+def test_c1_full_size_parity(gpu, oracle_mod):
+    """2048^2 with 20 crystals, in the default launch configuration, elementwise."""
+    _compare(gpu, oracle_mod, W.c1(), 12)
+
+
+# ---------------------------------------------------------------------------
+# Full-size 512^3 in the benchmark's launch configuration: a node's update
+# depends on its 2-hop neighbourhood only, so after k steps the nodes farther
+# than 2k from the walls of an oracle box centred on the seed see exactly the
+# 512^3 problem.  Compare that window.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,tol", [("fp64", FP64_TOL), ("fp16", 2e-3)])
+def test_c3_full_size_window(gpu, oracle_mod, storage, tol):
+    import torch
+    k, half = 6, 26
+    cfg = W.c3(storage, "110")
+    _say(_case(cfg, k) + " (window parity)")
+    sim = gpu.Simulation(cfg)
+    sim.step(k)
+    phi, u, _ = sim.fields()
+    c = cfg.nx // 2
+    sl = slice(c - half, c + half)
+    gphi = phi[sl, sl, sl].cpu().numpy()
+    gu = u[sl, sl, sl].cpu().numpy()
+    del sim, phi, u
+    torch.cuda.empty_cache()
+    n = 2 * half
+    wcfg = cfg.replace(nx=n, ny=n, nz=n, storage="fp64", seeds=[W.Seed(half, half, half, 8.0, 1)])
+    orc = _oracle_run(oracle_mod, wcfg, k)
+    inner = slice(2 * k, n - 2 * k)
+    ephi = np.abs(gphi[inner, inner, inner] - orc.phi()[inner, inner, inner]).max()
+    eu = np.abs(gu[inner, inner, inner] - orc.u()[inner, inner, inner]).max()
+    _say(f"  window max|dphi| = {ephi:.3e}  max|du| = {eu:.3e}")
+    assert ephi <= tol and eu <= tol
+
+
+# ---------------------------------------------------------------------------
+# Offset storage (FP32 arithmetic, FP32 / FP16 offsets) against the FP64 oracle.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,tol_phi,tol_u", [("fp32", 1e-4, 1e-4), ("fp16", 2e-3, 2e-3)])
+def test_c0_offset_storage_accuracy(gpu, oracle_mod, storage, tol_phi, tol_u):
+    cfg = W.c0(storage)
+    _say(_case(cfg, W.C0_STEPS))
+    sim, phi, u, _ = _gpu_run(gpu, cfg, W.C0_STEPS)
+    orc = _oracle_run(oracle_mod, cfg, W.C0_STEPS)
+    ephi = np.abs(phi - orc.phi()).max()
+    eu = np.abs(u - orc.u()).max()
+    dg, do = sim.diagnostics()[0], orc.diagnostics()
+    etip = abs(dg["tip_position"] - do["tip_position"])
+    efs = abs(dg["solid_fraction"] - do["solid_fraction"])
+    _say(f"  {storage}: max|dphi| = {ephi:.3e} max|du| = {eu:.3e} |dtip| = {etip:.3e} |dfs| = {efs:.3e}")
+    assert ephi <= tol_phi and eu <= tol_u and etip < 0.1
+
+
+@pytest.mark.parametrize("storage,tol", [("fp32", 1e-4), ("fp16", 2e-3)])
+def test_3d_offset_storage_accuracy(gpu, oracle_mod, storage, tol):
+    cfg = W.small_3d(storage=storage, n=40, radius=6)
+    _say(_case(cfg, 100))
+    sim, phi, u, _ = _gpu_run(gpu, cfg, 100)
+    orc = _oracle_run(oracle_mod, cfg, 100)
+    ephi = np.abs(phi - orc.phi()).max()
+    eu = np.abs(u - orc.u()).max()
+    _say(f"  {storage}: max|dphi| = {ephi:.3e} max|du| = {eu:.3e}")
+    assert ephi <= tol and eu <= tol
+
+
+# ---------------------------------------------------------------------------
+# Launch shape, determinism, checkpoint, batching.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,tiles", [("fp64", [(2, 8), (4, 64), (4, 5)]),
+                                           ("fp16", [(2, 16), (4, 7), (8, 64)])])
+def test_tile_shapes_bitwise_equal(gpu, storage, tiles):
+    cfg = W.small_3d(storage=storage, nx=70, ny=37, nz=29, radius=6)
+    outs = []
+    for t in tiles:
+        _say(_case(cfg, 15) + f" tile={t}")
+        _, phi, u, _ = _gpu_run(gpu, cfg, 15, tile=t)
+        outs.append((phi, u))
+    for phi, u in outs[1:]:
+        assert np.array_equal(phi, outs[0][0]) and np.array_equal(u, outs[0][1])
+
+
+def test_two_runs_bitwise_equal(gpu):
+    cfg = W.c1(n=192, count=6, storage="fp16")
+    _say(_case(cfg, 100) + " x2")
+    a = _gpu_run(gpu, cfg, 100)
+    b = _gpu_run(gpu, cfg, 100)
+    for x, y in zip(a[1:], b[1:]):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("storage", ["fp64", "fp16"])
+def test_checkpoint_restart_bitwise(gpu, storage):
+    import torch
+    cfg = W.c1(n=128, count=3, storage=storage)
+    _say(_case(cfg, 50) + " checkpoint")
+    sim = gpu.Simulation(cfg)
+    sim.step(30)
+    ck = sim.save_state()
+    sim.step(20)
+    a = [t.cpu().numpy() for t in sim.fields()]
+    sim.load_state(ck)
+    sim.step(20)
+    b = [t.cpu().numpy() for t in sim.fields()]
+    torch.cuda.synchronize()
+    straight = _gpu_run(gpu, cfg, 50)[1:]
+    for x, y, z in zip(a, b, straight):
+        assert np.array_equal(x, y) and np.array_equal(x, z)
+
+
+def test_batched_handle_matches_individual_runs(gpu):
+    cfgs = W.c4(count=3, side_hi=4)
+    _say("batched ensemble of 3 fp32 2D sims, 40 steps")
+    import torch
+    sim = gpu.Simulation(cfgs)
+    sim.step(40)
+    for k, cfg in enumerate(cfgs):
+        phi, u, _ = sim.fields(k)
+        _, p1, u1, _ = _gpu_run(gpu, cfg, 40)
+        assert np.array_equal(phi.cpu().numpy(), p1) and np.array_equal(u.cpu().numpy(), u1)
+    d = sim.diagnostics()
+    assert len(d) == 3 and all(x["step"] == 40 for x in d)
+    torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------------------
+# Properties that hold at any size.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_conservation_periodic(gpu, storage, tol):
+    cfg = W.c0(storage=storage, n=96)
+    _say(_case(cfg, 400) + " conservation")
+    sim = gpu.Simulation(cfg)
+    c0 = sim.diagnostics()[0]["sum_u_minus_half_phi"]
+    sim.step(400)
+    d = sim.diagnostics()[0]
+    assert abs(d["sum_u_minus_half_phi"] - c0) <= tol * cfg.nodes * 400
+
+
+def test_import_gaussian_diffusion(gpu, oracle_mod):
+    import torch
+    cfg = W.small_3d(n=32, boundary="periodic").replace(seeds=[])
+    _say(_case(cfg, 12) + " gaussian import")
+    z, y, x = np.meshgrid(*[np.arange(32) - 16] * 3, indexing="ij")
+    r2 = (x**2 + y**2 + z**2).astype(float)
+    bump = np.exp(-r2 / 32.0)
+    bump[r2 > 15**2 - 1] = 0.0
+    sim = gpu.Simulation(cfg)
+    sim.import_fields(-np.ones((32, 32, 32)), bump)
+    sim.step(12)
+    _, u, _ = sim.fields()
+    orc = oracle_mod.OracleSim(cfg)
+    orc.set_fields(-np.ones((32, 32, 32)), bump)
+    orc.step(12)
+    assert np.abs(u.cpu().numpy() - orc.u()).max() < 1e-13
+    torch.cuda.synchronize()
+
+
+def test_nonfinite_is_reported(gpu):
+    import paper_1606_09432_amd as lb
+    cfg = W.c0(n=32)
+    _say("non-finite import")
+    sim = gpu.Simulation(cfg)
+    phi = np.full((32, 32), -1.0)
+    phi[3, 4] = np.nan
+    sim.import_fields(phi, np.zeros((32, 32)))
+    with pytest.raises(lb.LbpfError) as ei:
+        sim.diagnostics()
+    assert ei.value.code == -5
+    assert sim.diagnostics(allow_nonfinite=True)[0]["nonfinite"] == 1
+
+
+def test_rotation_invariance_gpu(gpu):
+    """90 degree rotation about the seed centre (exact for the method, to
+    rounding on the GPU where fused multiply-adds break bitwise symmetry)."""
+    cfg = W.c0(n=96, storage="fp64").replace(aniso=[W.Aniso("sectoral", 0.05, 4, math.radians(20))])
+    _say(_case(cfg, 500) + " rotation")
+    _, phi, u, _ = _gpu_run(gpu, cfg, 500)
+    c = 48
+    y, x = np.meshgrid(np.arange(96), np.arange(96), indexing="ij")
+    assert np.abs(phi[x, (2 * c - y) % 96] - phi).max() < 1e-12
