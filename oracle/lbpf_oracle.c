@@ -35,7 +35,12 @@
  *     takes the post-collision g_i'* of the same node (no nonlocal term).  The
  *     same rule holds for f.  Ghost phi values for gradients are mirrored about
  *     the wall node: phi(-1) = phi(1).
- *   - |p|^2 <= 1e-24 (lattice units): n is undefined, a_s = 1, N = 0.
+ *   - |p| <= 1e-8 (lattice units): n is taken as undefined, a_s = 1, N = 0.
+ *     The paper leaves n = -grad phi/|grad phi| undefined where the gradient
+ *     vanishes.  Below 1e-8 the FP64 rounding of the phi differences (about
+ *     1e-16) decides the direction of n, and a_s(n), which varies by O(eps)
+ *     with the direction, would turn rounding into O(eps) changes of the local
+ *     relaxation; the bulk there is within 1e-8 of +-1, with no interface.
  *   - Crystal index: a node with I = 0 whose gradient exceeds xi takes the
  *     index of the phi-lattice neighbour with nonzero index and largest phi
  *     (ties: smaller index); the updated index is used in the same step.
@@ -228,7 +233,7 @@ void orc_flux(const orc_aniso *an, const double p[3], double *a, double N[3]) {
   *a = 1.0;
   if (an == NULL || an->kind == ORC_ANISO_ISO) return;
   const double r2 = (p[0] * p[0] + p[1] * p[1]) + p[2] * p[2];
-  if (!(r2 > 1e-24)) return;
+  if (!(r2 > 1e-16)) return;
   const double r = sqrt(r2);
   const double n[3] = {-p[0] / r, -p[1] / r, -p[2] / r};
   double G[3];

@@ -204,14 +204,16 @@ __device__ __forceinline__ void aniso_eval(const AnisoDev &A, T nx, T ny, T nz, 
 }
 
 // a_s and N = -|p| a (G - n (n.G)) for the gradient p, n = -p/|p|
-// (Eqs. Def_Normal_Vector, TermesAnisotropes).  Isotropic when |p|^2 <= 1e-24.
+// (Eqs. Def_Normal_Vector, TermesAnisotropes).  Isotropic where |p| <= 1e-8
+// (lattice units): below that the direction of p is set by the rounding of
+// phi differences rather than by an interface, and a_s depends on it at O(eps).
 template <class T>
 __device__ __forceinline__ void flux(const AnisoDev *A, T px, T py, T pz, T &a, T &Nx, T &Ny, T &Nz) {
   a = T(1);
   Nx = Ny = Nz = T(0);
   if (A == nullptr || A->kind == K_ISO) return;
   const T r2 = (px * px + py * py) + pz * pz;
-  if (!(r2 > T(1e-24))) return;
+  if (!(r2 > T(1e-16))) return;
   const T r = sqrt(r2);
   const T ir = T(1) / r;
   const T nx = -px * ir, ny = -py * ir, nz = -pz * ir;

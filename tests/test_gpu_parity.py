@@ -50,7 +50,11 @@ def _compare(lb, O, cfg, steps, tol=FP64_TOL, tile=None):
     orc = _oracle_run(O, cfg, steps)
     ephi = np.abs(phi - orc.phi()).max()
     eu = np.abs(u - orc.u()).max()
-    _say(f"  max|dphi| = {ephi:.3e}  max|du| = {eu:.3e}")
+    _say(f"  max|dphi| = {ephi:.3e} at {np.unravel_index(np.abs(phi - orc.phi()).argmax(), phi.shape)}"
+         f"  max|du| = {eu:.3e}")
+    if cfg.use_ids:
+        bad = ids != orc.ids()
+        _say(f"  index mismatches: {int(bad.sum())} at {np.argwhere(bad)[:5].tolist()}")
     assert ephi <= tol and eu <= tol, (ephi, eu)
     if cfg.use_ids:
         assert np.array_equal(ids, orc.ids())
@@ -88,6 +92,11 @@ def test_2d_distributions_parity(gpu, oracle_mod):
     sim, _, _, _ = _gpu_run(gpu, cfg, 50)
     g, f = sim.dists()
     orc = _oracle_run(oracle_mod, cfg, 50)
+    dg = np.abs(g.cpu().numpy() - orc.g())
+    loc = np.unravel_index(dg.argmax(), dg.shape)
+    _say(f"  max|dg| = {dg.max():.3e} at (i, y, x) = {loc}; nodes with |dg| > 1e-12: "
+         f"{np.argwhere(dg.max(0) > 1e-12)[:8].tolist()}  dirs: {sorted(set(np.argwhere(dg > 1e-12)[:, 0].tolist()))}")
+    _say(f"  max|dphi| = {np.abs(sim.fields()[0].cpu().numpy() - orc.phi()).max():.3e}")
     assert np.abs(g.cpu().numpy() - orc.g()).max() < 1e-12
     assert np.abs(f.cpu().numpy() - orc.f()).max() < 1e-12
 

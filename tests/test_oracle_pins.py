@@ -682,3 +682,33 @@ def test_tip_position_definition(oracle_mod):
     ph[10, 10, 10] = -0.5  # crossing between k = 5 and k = 6 at 5 + 1/1.5
     s3.set_fields(ph, np.zeros_like(ph))
     assert abs(s3.diagnostics()["tip_position"] - (5 + 1 / 1.5) * math.sqrt(3)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Conditioning of the |grad phi| -> 0 limit (reading: n undefined, a_s = 1 and
+# N = 0 where |grad phi| <= 1e-8 lattice units).  A 1e-15 perturbation must
+# stay at rounding level instead of being amplified through noise-dominated
+# normals in the far field of a seed.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("node", [(2, 48), (60, 60)])
+def test_far_field_is_well_conditioned(oracle_mod, node):
+    cfg = W.c0(n=72).replace(boundary="zero_flux", seeds=[W.Seed(20, 30, 0, 6, 1)])
+    a = oracle_mod.OracleSim(cfg)
+    b = oracle_mod.OracleSim(cfg)
+    phi = b.phi().copy()
+    phi[node] += 1e-15
+    b.set_fields(phi, b.u())
+    worst = 0.0
+    for _ in range(6):
+        a.step(10)
+        b.step(10)
+        worst = max(worst, float(np.abs(a.phi() - b.phi()).max()))
+    assert worst < 1e-12, worst
+
+
+def test_isotropic_below_gradient_cutoff(oracle_mod):
+    entry = W.Aniso("cubic_hak", eps=0.1, gamma=-0.02)
+    a, N = oracle_mod.flux(entry, np.array([6e-9, 5e-9, 0.0]))
+    assert a == 1.0 and not N.any()
+    a, N = oracle_mod.flux(entry, np.array([2e-8, 1e-8, 0.0]))
+    assert a != 1.0 and N.any()
