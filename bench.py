@@ -14,9 +14,11 @@ oracle timed on a bounded sample on the host cores.
 from __future__ import annotations
 
 import argparse
+import glob
 import hashlib
 import json
 import os
+import sqlite3
 import sys
 import time
 
@@ -112,19 +114,136 @@ def cpu_baseline(cfg_full, sample_n: int, sample_steps: int):
                       f"{dt:.1f} s"}
 
 
+# -- rocprofv3 summaries ---------------------------------------------------------
+# The profiler writes one SQLite database (*_results.db) per process; these
+# helpers turn them into the short text summaries kept next to the numbers.
+STORAGE_OF_KERNEL = {"StF64": "fp64", "StF32": "fp32", "StF16": "fp16"}
+
+
+def _dbs(d):
+    return sorted(glob.glob(os.path.join(d, "**", "*_results.db"), recursive=True))
+
+
+def _short(name):
+    return name.split("(")[0].replace("void ", "").replace("lbpf::", "")
+
+
+def summarize_trace(d, command, bench_json=None):
+    """Per-kernel dispatch statistics (--kernel-trace) as markdown."""
+    rows = {}
+    for db in _dbs(d):
+        con = sqlite3.connect(db)
+        q = ("SELECT S.display_name, K.end - K.start FROM rocpd_kernel_dispatch K "
+             "JOIN rocpd_info_kernel_symbol S ON S.id = K.kernel_id AND S.guid = K.guid")
+        for name, dur in con.execute(q):
+            rows.setdefault(_short(name), []).append(dur)
+    out = ["# Kernel trace: " + ", ".join(sorted(k for k in rows if "step_kernel" in k)), "",
+           "Command (from the repository root):", "", "```", command, "```", "",
+           "| kernel | calls | avg ms | min ms | max ms | total ms |", "|---|---|---|---|---|---|"]
+    for k, v in sorted(rows.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"| `{k}` | {len(v)} | {sum(v) / len(v) / 1e6:.4f} | {min(v) / 1e6:.4f} | "
+                   f"{max(v) / 1e6:.4f} | {sum(v) / 1e6:.3f} |")
+    if bench_json:
+        b = json.loads(open(bench_json).read().strip().splitlines()[-1])
+        out += ["", "bench.py's own HIP-event figures in the same run (ms per step = per launch):", ""]
+        out.append(f"- {b['config']['storage']}: {b['ms_per_step']:.4f} ms, {b['value']:.1f} {b['unit']}, "
+                   f"{b['roofline']['achieved']:.0f} GB/s algorithmic")
+        for st in ("fp64", "fp32", "fp16"):
+            if st in b:
+                out.append(f"- {st}: {b[st]['ms_per_step']:.4f} ms, {b[st]['value']:.1f} {b[st]['unit']}, "
+                           f"{b[st]['roofline']['achieved']:.0f} GB/s algorithmic")
+    return "\n".join(out) + "\n"
+
+
+def _pmc(d):
+    """{kernel: {counter: mean over dispatches of the per-dispatch sum}}."""
+    acc = {}
+    for db in _dbs(d):
+        con = sqlite3.connect(db)
+        q = ("SELECT name, dispatch_id, counter_name, SUM(counter_value) FROM pmc_events "
+             "GROUP BY dispatch_id, counter_name")
+        for name, _disp, cn, v in con.execute(q):
+            acc.setdefault(_short(name), {}).setdefault(cn, []).append(v)
+    return {k: {cn: sum(v) / len(v) for cn, v in c.items()} for k, c in acc.items()}
+
+
+def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, command):
+    """HBM bytes per launch of the step kernel from FETCH_SIZE / WRITE_SIZE,
+    each scaled by what the counter reads for a plain copy of copy_bytes."""
+    fe, wr, cf, cw = _pmc(fetch_dir), _pmc(write_dir), _pmc(cfetch_dir), _pmc(cwrite_dir)
+    copy_f = max(v.get("FETCH_SIZE", 0.0) for v in cf.values())
+    copy_w = max(v.get("WRITE_SIZE", 0.0) for v in cw.values())
+    ff, fw = copy_bytes / copy_f, copy_bytes / copy_w
+    sha = kernel_sha()
+    res = {"kernel_sha": sha, "copy_bytes": copy_bytes, "copy_fetch_counter": copy_f,
+           "copy_write_counter": copy_w, "factor_fetch": ff, "factor_write": fw, "command": command,
+           "kernels": {}}
+    md = ["# HBM traffic of the step kernel (rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE)", "",
+          "Commands (from the repository root):", "", "```", command, "```", "",
+          f"Calibration: a plain copy of {copy_bytes} bytes reads FETCH_SIZE = {copy_f:.0f} and "
+          f"WRITE_SIZE = {copy_w:.0f}, so bytes = FETCH_SIZE x {ff:.1f} + WRITE_SIZE x {fw:.1f}.", "",
+          "| kernel | FETCH_SIZE | WRITE_SIZE | read bytes | written bytes | bytes/launch | bytes/node |",
+          "|---|---|---|---|---|---|---|"]
+    for k in sorted(set(fe) | set(wr)):
+        if "step_kernel" not in k:
+            continue
+        st = next((v for kk, v in STORAGE_OF_KERNEL.items() if kk in k), None)
+        f, w = fe.get(k, {}).get("FETCH_SIZE"), wr.get(k, {}).get("WRITE_SIZE")
+        if st is None or f is None or w is None:
+            continue
+        rb, wb = f * ff, w * fw
+        nodes = 512 ** 3
+        res["kernels"][st] = {"kernel": k, "kernel_sha": sha, "fetch_counter": f, "write_counter": w,
+                              "read_bytes": rb, "write_bytes": wb, "bytes_per_launch": rb + wb,
+                              "bytes_per_node": (rb + wb) / nodes}
+        md.append(f"| `{k}` | {f:.0f} | {w:.0f} | {rb:.4g} | {wb:.4g} | {rb + wb:.4g} | "
+                  f"{(rb + wb) / nodes:.1f} |")
+    md += ["", f"Kernel source hash: {sha} (bench.py reports this traffic only while it matches)."]
+    return res, "\n".join(md) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=512, help="grid side (the workload is 512)")
     ap.add_argument("--variant", default="100", choices=["100", "111", "110"])
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=96)
-    ap.add_argument("--cpu-steps", type=int, default=30)
+    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--cpu-steps", type=int, default=100)
     ap.add_argument("--only", choices=["fp16", "fp64", "fp32"], default=None)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (for HBM counter calibration)")
+    ap.add_argument("--summarize-trace", metavar="DIR", help="write a markdown summary of a --kernel-trace run")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="write profiles/hbm_traffic.json from four --pmc runs")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--command", default="", help="the profiling command, recorded in the summary")
+    ap.add_argument("--bench-json", default=None)
+    ap.add_argument("--out", default=None)
     args = ap.parse_args()
+    if args.summarize_trace:
+        text = summarize_trace(args.summarize_trace, args.command, args.bench_json)
+        open(args.out, "w").write(text) if args.out else print(text)
+        return
+    if args.summarize_traffic:
+        res, md = summarize_traffic(*args.summarize_traffic, args.copy_mib * (1 << 20), args.command)
+        json.dump(res, open(TRAFFIC_FILE, "w"), indent=1)
+        open(args.out, "w").write(md) if args.out else print(md)
+        return
+    if args.calibrate_copy:
+        # a plain elementwise copy kernel (read n bytes, write n bytes)
+        import torch
+        n = args.calibrate_copy * (1 << 20)
+        src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the z-slab sharding is a "
               "design note only); run with --gpus 1", file=sys.stderr)

@@ -16,7 +16,9 @@ from . import workloads
 from .workloads import Aniso, Seed, SimConfig
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbpf.so")
+# LBPF_LIBRARY selects another build of the same library (e.g. to compare two
+# kernel versions); the default is the in-tree build.
+LIB_PATH = os.environ.get("LBPF_LIBRARY", os.path.join(HERE, "liblbpf.so"))
 
 __all__ = ["Simulation", "SimConfig", "Aniso", "Seed", "workloads", "load_library", "sharp_interface",
            "LbpfError", "EXPORTED_SYMBOLS"]
@@ -183,12 +185,20 @@ class Simulation:
     def _stream(self):
         return C.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
 
-    def __del__(self):
+    def close(self) -> None:
+        """Waits for the enqueued work and frees the handle (the workspace
+        tensor goes with the object)."""
         h = getattr(self, "h", None)
         if h is not None and h.value:
             self.torch.cuda.current_stream(self.device).synchronize()
             self.lib.lb_pf_destroy(h)
-            self.h = None
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown: torch may already be torn down
+            pass
 
     # -- stepping ----------------------------------------------------------------
     def step(self, n: int = 1) -> None:

@@ -66,7 +66,12 @@ int validate(const lbpf_config &c) {
   if (c.nx < 3 || c.ny < 3) return fail(LBPF_ERR_ARG, "nx and ny must be >= 3");
   if (dim == 2 && c.nz != 1) return fail(LBPF_ERR_ARG, "nz must be 1 for the 2D lattice pair");
   if (dim == 3 && c.nz < 3) return fail(LBPF_ERR_ARG, "nz must be >= 3 in 3D");
-  if ((long long)c.nx * c.ny * c.nz > (1LL << 31) * 4) return fail(LBPF_ERR_ARG, "grid too large");
+  {
+    const long long elems = (long long)((c.nx + 63) / 64 * 64) * c.ny * c.nz;
+    const long long esize = c.storage == LBPF_FP64 ? 8 : 4;
+    if (elems * esize >= (1LL << 32))
+      return fail(LBPF_ERR_ARG, "grid too large: one field must stay below 4 GiB (32-bit byte offsets)");
+  }
   if (c.boundary != LBPF_PERIODIC && c.boundary != LBPF_ZERO_FLUX) return fail(LBPF_ERR_ARG, "unknown boundary");
   if (c.gradient != LBPF_GRAD_DD && c.gradient != LBPF_GRAD_CD) return fail(LBPF_ERR_ARG, "unknown gradient");
   if (c.storage < LBPF_FP64 || c.storage > LBPF_FP16_OFFSET) return fail(LBPF_ERR_ARG, "unknown storage");
@@ -126,7 +131,7 @@ int set_tile(SimHost &s, int ty, int chunk) {
   TileDev t = s.tile;
   if (ty > 0) {
     if (s.dim == 2 && ty != 1) return fail(LBPF_ERR_UNSUPPORTED, "2D tiles are one row high");
-    if (s.dim == 3 && ty != 2 && ty != 4 && ty != 8) return fail(LBPF_ERR_UNSUPPORTED, "tile_y must be 2, 4 or 8");
+    if (s.dim == 3 && ty != 4 && ty != 8) return fail(LBPF_ERR_UNSUPPORTED, "tile_y must be 4 or 8");
     if (s.dim == 3 && ty == 8 && s.storage == LBPF_FP64) return fail(LBPF_ERR_UNSUPPORTED, "tile_y 8 needs FP32 arithmetic");
     t.ty = ty;
   }
@@ -481,7 +486,7 @@ int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream) {
   if (steps_per_trial < 1) return fail(LBPF_ERR_ARG, "steps_per_trial < 1");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const SimHost &s0 = h->sims[0];
-  std::vector<int> tys = s0.dim == 3 ? std::vector<int>{2, 4, 8} : std::vector<int>{1};
+  std::vector<int> tys = s0.dim == 3 ? std::vector<int>{4, 8} : std::vector<int>{1};
   std::vector<int> chunks = s0.dim == 3 ? std::vector<int>{16, 32, 64, 128} : std::vector<int>{16, 32, 64, 128};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));

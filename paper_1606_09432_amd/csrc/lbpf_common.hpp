@@ -151,9 +151,19 @@ __device__ __forceinline__ int ghost(int c, int n, int periodic) {
 }
 __device__ __forceinline__ int wrapc(int c, int n) { return c < 0 ? c + n : (c >= n ? c - n : c); }
 
-__device__ __forceinline__ long long lin(const SimDev &sd, int x, int yp, int m) {
-  return (long long)m * sd.mstride + (long long)yp * sd.pitch + x;
+// Element offset of node (x, yp, m) inside one field.  A field holds fewer
+// than 2^31 elements (checked when the workspace is planned), so the offset is
+// a 32-bit value added to a per-field base pointer.
+__device__ __forceinline__ unsigned lin(const SimDev &sd, int x, int yp, int m) {
+  return (unsigned)m * (unsigned)sd.mstride + (unsigned)yp * (unsigned)sd.pitch + (unsigned)x;
 }
+
+// Reciprocal and reciprocal square root: exact in FP64 (parity with the FP64
+// reference), the hardware approximations (about 1 ulp) in FP32.
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rsqrt_(double x) { return 1.0 / sqrt(x); }
+__device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(x); }
 
 // ---------------------------------------------------------------------------
 // Anisotropy functions (Sec. 4.1): value a and gradient G of the polynomial in n.
@@ -214,8 +224,8 @@ __device__ __forceinline__ void flux(const AnisoDev *A, T px, T py, T pz, T &a, 
   if (A == nullptr || A->kind == K_ISO) return;
   const T r2 = (px * px + py * py) + pz * pz;
   if (!(r2 > T(1e-16))) return;
-  const T r = sqrt(r2);
-  const T ir = T(1) / r;
+  const T ir = rsqrt_(r2);
+  const T r = r2 * ir;
   const T nx = -px * ir, ny = -py * ir, nz = -pz * ir;
   T Gx, Gy, Gz;
   aniso_eval<T>(*A, nx, ny, nz, a, Gx, Gy, Gz);
@@ -242,7 +252,7 @@ __device__ __forceinline__ typename ST::T gather_u(const SimDev &sd, int x, int 
   using T = typename ST::T;
   using LU = typename Lat<DIM>::U;
   const typename ST::S *F = reinterpret_cast<const typename ST::S *>(sd.f_in);
-  const long long self = lin(sd, x, yp, m);
+  const unsigned self = lin(sd, x, yp, m);
   T us_self = T(0);
   if constexpr (ST::OFF) us_self = sd.us_in[self];
   T sum = T(0);
@@ -250,7 +260,7 @@ __device__ __forceinline__ typename ST::T gather_u(const SimDev &sd, int x, int 
   for (int i = 0; i < LU::Q; ++i) {
     int sx = x - ex<LU, DIM>(i), sy = yp - ey<LU, DIM>(i), sm = m - em<LU, DIM>(i);
     int d = i;
-    long long src;
+    unsigned src;
     if (sd.periodic) {
       src = lin(sd, wrapc(sx, sd.nx), DIM == 3 ? wrapc(sy, sd.nyp) : 0, wrapc(sm, sd.nm));
     } else if (in_range(sx, sd.nx) && (DIM == 2 || in_range(sy, sd.nyp)) && in_range(sm, sd.nm)) {

@@ -2,25 +2,32 @@
 //
 // One launch advances one simulation by one time step.  A work-group owns a
 // 64 x TY tile of the plane perpendicular to the march axis m (z in 3D, y in
-// 2D; TY = 1 in 2D) and walks `chunk` planes along m.  Per plane it
-//   1. stages phi^n of plane m+2 (tile + 2-node halo) in an LDS ring of 4 planes,
-//   2. computes, for plane m+1 on the tile + 1-node halo, the gradient of phi
-//      (directional derivatives, Eqs. Def_DeriveeDirectionnelle and
+// 2D; TY = 1 in 2D) and walks `chunk` planes along m.  For output plane m it
+//   A. computes, for plane m+1 on the tile + 1-node halo, the gradient of
+//      phi^n (directional derivatives, Eqs. Def_DeriveeDirectionnelle and
 //      Grad_DF-Centree, or central differences), the crystal index update
 //      (Sec. 4.3), u^n by gathering the heat populations, a_s and N
 //      (Eq. TermesAnisotropes), eta_phi (Eq. LBE_RelaxationTime) and Q_phi
-//      (Eq. LBE_SourceTerm), folded into six per-node coefficients kept in an
-//      LDS ring of 3 planes,
-//   3. for every node y of plane m pulls g_i from x = y - e_i with the nonlocal
+//      (Eq. LBE_SourceTerm), folded into per-node coefficients kept in an LDS
+//      ring of 3 planes;
+//   B. for every node y of plane m pulls g_i from x = y - e_i with the nonlocal
 //      a_s^2 form of Eq. LBE_Eq_Phase,
 //        g_i(y, t+1) = g_i(y, t) + [g*_i(x) - g_i(y, t)] / a_s^2(x),
 //        g*_i(x)    = (1 - w) g_i(x) + w g^(0)_i(x) + w_i Q_phi(x) dt/tau0,
 //      applies bounce-back on the walls (Eq. Bounce-Back), sums phi^{n+1}
-//      (Eq. Def_M0_Phi), then collides the heat populations with the source
+//      (Eq. Def_M0_Phi), collides the heat populations with the source
 //      (phi^{n+1} - phi^n)/2 (Eqs. LBE_Eq_Temp, Source_Tempr) and stores them
 //      post-collision at y ("stream on read": the next step pulls them).
-// Every distribution is read from HBM once and written once per step; the
-// second, shifted read of g_i(x) and the halo gathers hit L2.
+// Latency: the loads of the next planes -- the heat populations gathered by
+// the coefficient nodes of plane m+2 and plane m+3 of the phi / u* / index
+// rings (5 or 4 planes, 2-node halo) -- are issued at the top of the
+// iteration and land while A runs from LDS and registers; B issues its g
+// loads in one batch.  Index and boundary logic is branch-free (selects) so
+// that loads are never serialised behind branches.  Two work-group barriers
+// per plane.  Every distribution is read
+// from HBM once and written once per step; the shifted read of g_i(x) and
+// the halo gathers hit L2.  Tiles whose halo stays inside the box take a path
+// without boundary checks.
 //
 // Offset storage (FP32 arithmetic): h_i = g_i - w_i phi and
 // k_i = f*_i - w_i u* are stored in FP32 or FP16 beside FP32 phi and u*; the
@@ -28,7 +35,8 @@
 //   h*_i(x) = A h_i(x) + w_i (Q s + e_i . C),  A = 1 - w,  C = -w (Dphi/e^2) N
 //   d_i     = h_i(y) + [w_i (phi(x) - phi(y)) + h*_i(x) - h_i(y)] / a^2(x)
 //   phi^{n+1}(y) = phi^n(y) + sum_i d_i,   h_i^{n+1}(y) = d_i - w_i sum_j d_j.
-#include "lbpf_common.hpp"
+#include <type_traits>
+
 #include "lbpf_kernels.hpp"
 
 namespace lbpf {
@@ -42,12 +50,28 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + k;
 }
 
+// Loads and stores at a 32-bit byte offset from a uniform base pointer, so that
+// the address is an SGPR base plus one VGPR offset (no 64-bit address math).
+template <class E> __device__ __forceinline__ E ldb(const E *base, unsigned boff) {
+  return *reinterpret_cast<const E *>(reinterpret_cast<const char *>(base) + boff);
+}
+template <class E> __device__ __forceinline__ void stb(E *base, unsigned boff, E v) {
+  *reinterpret_cast<E *>(reinterpret_cast<char *>(base) + boff) = v;
+}
+
+// Minimum waves per SIMD the register allocator must leave room for.
+template <int DIM, int TY, class ST> constexpr int min_waves() {
+  return DIM == 2 ? 4 : (std::is_same<ST, StF64>::value ? 2 : (TY == 8 ? 4 : 3));
+}
+
 template <int DIM, int TY, class ST, bool IDS>
-__global__ __launch_bounds__(64 * TY) void step_kernel(SimDev sd, TileDev tc) {
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(min_waves<DIM, TY, ST>(), 8))) void
+step_kernel(SimDev sd, TileDev tc) {
   using T = typename ST::T;
   using LP = typename Lat<DIM>::P;
   using LU = typename Lat<DIM>::U;
   using S = typename ST::S;
+  using PT = typename ST::P;
   constexpr int TX = 64;
   constexpr int NT = TX * TY;
   constexpr int HX = TX + 2, HY = (DIM == 3 ? TY + 2 : 1);
@@ -55,12 +79,17 @@ __global__ __launch_bounds__(64 * TY) void step_kernel(SimDev sd, TileDev tc) {
   constexpr int NP = DIM + 3;  // A, B, C[DIM], 1/a^2
   constexpr int PLANE_P = HX * HY;
   constexpr int PLANE_F = PX * PY;
-  constexpr int PYO = (DIM == 3) ? 1 : 0;  // row offset of a coefficient node in the phi ring
+  constexpr int NHALO = PLANE_P - NT;             // halo coefficient nodes per plane
+  constexpr int NLOAD = (PLANE_F + NT - 1) / NT;  // ring entries staged per thread
+  constexpr int PYO = (DIM == 3) ? 1 : 0;         // row offset of a coefficient node in the ring
   constexpr int QP = LP::Q, QU = LU::Q;
+  constexpr bool OFF = ST::OFF;
+  static_assert(NHALO <= NT, "one halo coefficient node per thread at most");
 
-  __shared__ T phiS[4][PLANE_F];
-  __shared__ T parS[3][NP][PLANE_P];
+  __shared__ T phiS[5][PLANE_F];
+  __shared__ float usS[OFF ? 4 : 1][OFF ? PLANE_F : 1];
   __shared__ int16_t idS[IDS ? 4 : 1][IDS ? PLANE_F : 1];
+  __shared__ T parS[3][NP][PLANE_P];
 
   const int tx = threadIdx.x;
   const int ty = (DIM == 3) ? threadIdx.y : 0;
@@ -76,162 +105,287 @@ __global__ __launch_bounds__(64 * TY) void step_kernel(SimDev sd, TileDev tc) {
   const int m0 = chunk * tc.chunk;
   const int m1 = min(m0 + tc.chunk, sd.nm);
   const int per = sd.periodic;
+  // tiles whose pulls (output: 1-node halo) or gathers (coefficients: 2-node
+  // halo) stay inside the box without wrapping: plain constant offsets there
+  const bool xy_in1 = x0 >= 1 && x0 + TX + 1 <= sd.nx && (DIM == 2 || (y0 >= 1 && y0 + TY + 1 <= sd.nyp));
+  const bool xy_in2 = x0 >= 2 && x0 + TX + 2 <= sd.nx && (DIM == 2 || (y0 >= 2 && y0 + TY + 2 <= sd.nyp));
 
+  // (no __restrict__: the g loads of B must stay below the barrier that ends A,
+  // where they would otherwise be hoisted and held in registers through A)
   const S *Gin = reinterpret_cast<const S *>(sd.g_in);
   S *Gout = reinterpret_cast<S *>(sd.g_out);
+  const S *Fin = reinterpret_cast<const S *>(sd.f_in);
   S *Fout = reinterpret_cast<S *>(sd.f_out);
-  const typename ST::P *Phin = reinterpret_cast<const typename ST::P *>(sd.phi_in);
-  typename ST::P *Phout = reinterpret_cast<typename ST::P *>(sd.phi_out);
+  const PT *__restrict__ Phin = reinterpret_cast<const PT *>(sd.phi_in);
+  PT *__restrict__ Phout = reinterpret_cast<PT *>(sd.phi_out);
+  // per-direction field base pointers (uniform); node offsets are 32-bit
+  auto gfield = [&](int i) { return Gin + (size_t)i * (size_t)sd.fstride; };
+  auto gofield = [&](int i) { return Gout + (size_t)i * (size_t)sd.fstride; };
+  auto ffield = [&](int i) { return Fin + (size_t)i * (size_t)sd.fstride; };
+  auto fofield = [&](int i) { return Fout + (size_t)i * (size_t)sd.fstride; };
+  const int pitch = sd.pitch;
+  const int mstride = (int)sd.mstride;
+  // byte offset from a node to its neighbour -e (uniform)
+  auto boff_of = [&](int cx, int cy, int cm, int esize) { return -(cx + cy * pitch + cm * mstride) * esize; };
 
-  // ---- stage phi^n (and I^n) of plane pm, tile + 2-node halo --------------
-  auto load_plane = [&](int pm) {
-    const int slot = pm & 3;
+  // ---- the coefficient nodes of this thread: its own column, maybe one halo node
+  const int hx_o = tx + 1, hy_o = (DIM == 3) ? ty + 1 : 0;
+  const bool has_h = tid < NHALO;
+  int hx_h = 0, hy_h = 0;
+  if constexpr (DIM == 3) {
+    const int r = tid;
+    if (r < HX) {
+      hx_h = r;
+      hy_h = 0;
+    } else if (r < 2 * HX) {
+      hx_h = r - HX;
+      hy_h = HY - 1;
+    } else if (r < 2 * HX + TY) {
+      hx_h = 0;
+      hy_h = r - 2 * HX + 1;
+    } else {
+      hx_h = HX - 1;
+      hy_h = r - 2 * HX - TY + 1;
+    }
+  } else {
+    hx_h = (tid == 0) ? 0 : HX - 1;
+  }
+
+  // box coordinates of coefficient node (hx, hy) of plane pm; false when the
+  // node is never pulled from (outside the box, or beyond its one-node halo).
+  // The coordinates returned are always inside the box (clamped when invalid).
+  auto node_at = [&](int hx, int hy, int pm, int &gx, int &gy, int &gm) -> bool {
+    gx = x0 - 1 + hx;
+    gy = (DIM == 3) ? y0 - 1 + hy : 0;
+    gm = pm;
+    bool ok;
+    if (per) {
+      ok = gx <= sd.nx && (DIM == 2 || gy <= sd.nyp);
+      gx = wrapc(gx, sd.nx);
+      gy = (DIM == 3) ? wrapc(gy, sd.nyp) : 0;
+      gm = wrapc(gm, sd.nm);
+    } else {
+      ok = in_range(gx, sd.nx) && (DIM == 2 || in_range(gy, sd.nyp)) && in_range(gm, sd.nm);
+    }
+    gx = min(max(gx, 0), sd.nx - 1);
+    gy = (DIM == 3) ? min(max(gy, 0), sd.nyp - 1) : 0;
+    gm = min(max(gm, 0), sd.nm - 1);
+    return ok;
+  };
+
+  // heat population i pulled by node (gx, gy, gm): stored field d at node src,
+  // which sits at ring offset (ox, oy, om) from the node.  Bounce-back for
+  // sources outside the box (Eq. Bounce-Back): the opposite population pulled
+  // from y + e_i, or the node's own post-collision opposite population.
+  auto heat_src = [&](int gx, int gy, int gm, int i, unsigned &src, int &d, int &ox, int &oy, int &om) {
+    const int cx = ex<LU, DIM>(i), cy = ey<LU, DIM>(i), cm = em<LU, DIM>(i);
+    int sx = gx - cx, sy = gy - cy, sm = gm - cm;
+    bool in1;
+    if (per) {
+      sx = wrapc(sx, sd.nx);
+      sy = (DIM == 3) ? wrapc(sy, sd.nyp) : 0;
+      sm = wrapc(sm, sd.nm);
+      in1 = true;
+    } else {
+      in1 = in_range(sx, sd.nx) && (DIM == 2 || in_range(sy, sd.nyp)) && in_range(sm, sd.nm);
+    }
+    const int tx_ = gx + cx, ty_ = gy + cy, tm_ = gm + cm;
+    const bool in2 = in_range(tx_, sd.nx) && (DIM == 2 || in_range(ty_, sd.nyp)) && in_range(tm_, sd.nm);
+    const int rx = in1 ? sx : (in2 ? tx_ : gx);
+    const int ry = in1 ? sy : (in2 ? ty_ : gy);
+    const int rm = in1 ? sm : (in2 ? tm_ : gm);
+    src = lin(sd, rx, ry, rm);
+    d = in1 ? i : LU::OPP[i];
+    ox = in1 ? -cx : (in2 ? cx : 0);
+    oy = in1 ? -cy : (in2 ? cy : 0);
+    om = in1 ? -cm : (in2 ? cm : 0);
+  };
+
+  // ---- ring staging: plane pm of phi^n, u*, I^n (tile + 2-node halo) --------
+  T ph_pf[NLOAD];
+  float us_pf[NLOAD];
+  int16_t id_pf[NLOAD];
+  // Halo coordinates beyond [-2, n + 1] (ragged last tile) are never read by a
+  // node that matters: they are clamped so every load stays in the box.  The
+  // FP64 form keeps the in-plane part of each ring entry (the same on every
+  // plane) in registers; the offset forms recompute it, which measures faster
+  // there (fewer live registers).
+  unsigned ring_off[NLOAD];
+  bool ring_out[NLOAD];
+  auto ring_xy = [&](int j, unsigned &off, bool &out) {
+    const int k = min(tid + j * NT, PLANE_F - 1);
+    const int px = k % PX, py = k / PX;
+    const int rx = min(max(x0 - 2 + px, -2), sd.nx + 1);
+    const int ry = (DIM == 3) ? min(max(y0 - 2 + py, -2), sd.nyp + 1) : 0;
+    const int gx = ghost(rx, sd.nx, per);
+    const int gy = (DIM == 3) ? ghost(ry, sd.nyp, per) : 0;
+    off = (unsigned)gy * (unsigned)pitch + (unsigned)gx;
+    out = !per && (!in_range(rx, sd.nx) || (DIM == 3 && !in_range(ry, sd.nyp)));
+  };
+  if constexpr (!OFF) {
+#pragma unroll
+    for (int j = 0; j < NLOAD; ++j) ring_xy(j, ring_off[j], ring_out[j]);
+  }
+  auto ring_fetch = [&](int pm) {
     const int gm = ghost(pm, sd.nm, per);  // pm is always within [-2, nm + 1]
-    const bool mout = !in_range(pm, sd.nm);
-    for (int k = tid; k < PLANE_F; k += NT) {
-      const int px = k % PX, py = k / PX;
-      // halo coordinates beyond [-2, n + 1] (ragged last tile) are never read
-      // by a node that matters: clamp them so every load stays in the box
-      const int rx = min(max(x0 - 2 + px, -2), sd.nx + 1);
-      const int ry = (DIM == 3) ? min(max(y0 - 2 + py, -2), sd.nyp + 1) : 0;
-      const int gx = ghost(rx, sd.nx, per);
-      const int gy = (DIM == 3) ? ghost(ry, sd.nyp, per) : 0;
-      const long long idx = lin(sd, gx, gy, gm);
-      phiS[slot][k] = T(Phin[idx]);
-      if constexpr (IDS) {
-        const bool out = !per && (mout || !in_range(rx, sd.nx) || (DIM == 3 && !in_range(ry, sd.nyp)));
-        idS[slot][k] = out ? int16_t(0) : sd.id_in[idx];
+    const bool mout = !per && !in_range(pm, sd.nm);
+    const unsigned mo = (unsigned)gm * (unsigned)mstride;
+#pragma unroll
+    for (int j = 0; j < NLOAD; ++j) {
+      if (tid + j * NT >= PLANE_F) break;
+      unsigned off;
+      bool out;
+      if constexpr (!OFF) {
+        off = ring_off[j];
+        out = ring_out[j];
+      } else {
+        ring_xy(j, off, out);
+      }
+      const unsigned idx = mo + off;
+      ph_pf[j] = T(ldb(Phin, idx * (unsigned)sizeof(PT)));
+      if constexpr (OFF) us_pf[j] = ldb(sd.us_in, idx * 4u);
+      if constexpr (IDS) id_pf[j] = (mout || out) ? int16_t(0) : ldb(sd.id_in, idx * 2u);
+    }
+  };
+  // phi keeps 5 planes (B of plane m reads plane m-1 while plane m+3 is
+  // committed); u* and I^n, read in A only, keep 4
+  auto rs = [](int pm) { return (pm + 10) % 5; };
+  auto rs4 = [](int pm) { return (pm + 8) & 3; };
+  auto ring_commit = [&](int pm) {
+    const int slot = rs(pm), slot4 = rs4(pm);
+#pragma unroll
+    for (int j = 0; j < NLOAD; ++j) {
+      const int k = tid + j * NT;
+      if (k >= PLANE_F) break;
+      phiS[slot][k] = ph_pf[j];
+      if constexpr (OFF) usS[slot4][k] = us_pf[j];
+      if constexpr (IDS) idS[slot4][k] = id_pf[j];
+    }
+  };
+
+  // ---- heat populations gathered by a coefficient node (prefetched) ---------
+  S kv_o_c[QU], kv_h_c[QU], kv_o_n[QU], kv_h_n[QU];
+  auto gather_fetch = [&](int hx, int hy, int pm, S(&kv)[QU]) {
+    int gx, gy, gm;
+    node_at(hx, hy, pm, gx, gy, gm);
+    if (xy_in2 && pm >= 1 && pm + 1 < sd.nm) {
+      const unsigned ib = lin(sd, gx, gy, gm) * (unsigned)sizeof(S);
+#pragma unroll
+      for (int i = 0; i < QU; ++i)
+        kv[i] = ldb(ffield(i), ib + boff_of(ex<LU, DIM>(i), ey<LU, DIM>(i), em<LU, DIM>(i), sizeof(S)));
+    } else {
+#pragma unroll
+      for (int i = 0; i < QU; ++i) {
+        unsigned src;
+        int d, ox, oy, om;
+        heat_src(gx, gy, gm, i, src, d, ox, oy, om);
+        kv[i] = ldb(ffield(d), src * (unsigned)sizeof(S));
       }
     }
   };
 
-  // registers describing the own-column node of the plane being prepared
-  // (nxt) and of the plane being written (cur)
+  // own-column node of the plane being prepared (nxt) and written (cur)
   T fd_cur[QU], fd_nxt[QU];
   T u_cur = T(0), u_nxt = T(0), us_cur = T(0), us_nxt = T(0);
   int16_t id_cur = 0, id_nxt = 0;
 
-  // ---- per-node coefficients of plane pm into parameter slot ps -----------
-  auto compute_params = [&](int pm, int ps) {
-    for (int k = tid; k < PLANE_P; k += NT) {
-      int hx, hy;
-      if (k < NT) {  // own columns first: thread tid gets its own column
-        hx = (k % TX) + 1;
-        hy = (DIM == 3) ? (k / TX) + 1 : 0;
+  // ---- A: coefficients of node (hx, hy) of plane pm into coefficient slot ps
+  auto param_node = [&](int hx, int hy, int pm, int ps, const S(&kv)[QU], bool own_node) {
+    int gx, gy, gm;
+    if (!node_at(hx, hy, pm, gx, gy, gm)) return;
+    const int pc = (hy + PYO) * PX + (hx + 1);  // node in the ring
+    const int sl0 = rs(pm);
+    const T phc = phiS[sl0][pc];
+    // gradient of phi^n, lattice units
+    T p0 = T(0), p1 = T(0), p2 = T(0);
+    if (sd.grad_cd) {
+      p0 = (phiS[sl0][pc + 1] - phiS[sl0][pc - 1]) / T(2);
+      if constexpr (DIM == 3) {
+        p1 = (phiS[sl0][pc + PX] - phiS[sl0][pc - PX]) / T(2);
+        p2 = (phiS[rs(pm + 1)][pc] - phiS[rs(pm - 1)][pc]) / T(2);
       } else {
-        const int r = k - NT;
-        if constexpr (DIM == 3) {
-          if (r < HX) {
-            hx = r;
-            hy = 0;
-          } else if (r < 2 * HX) {
-            hx = r - HX;
-            hy = HY - 1;
-          } else if (r < 2 * HX + TY) {
-            hx = 0;
-            hy = r - 2 * HX + 1;
-          } else {
-            hx = HX - 1;
-            hy = r - 2 * HX - TY + 1;
-          }
-        } else {
-          hx = (r == 0) ? 0 : HX - 1;
-          hy = 0;
-        }
+        p1 = (phiS[rs(pm + 1)][pc] - phiS[rs(pm - 1)][pc]) / T(2);
       }
-      int gx = x0 - 1 + hx, gy = (DIM == 3) ? y0 - 1 + hy : 0, gm = pm;
-      // only nodes within one node of the box are ever pulled from
-      if (gx > sd.nx || (DIM == 3 && gy > sd.nyp)) continue;
-      if (per) {
-        gx = wrapc(gx, sd.nx);
-        if (DIM == 3) gy = wrapc(gy, sd.nyp);
-        gm = wrapc(gm, sd.nm);
-      } else if (!in_range(gx, sd.nx) || (DIM == 3 && !in_range(gy, sd.nyp)) || !in_range(gm, sd.nm)) {
-        continue;  // outside the box: never pulled from (bounce-back instead)
+    } else {
+#pragma unroll
+      for (int i = 1; i < QP; ++i) {
+        const int o = ey<LP, DIM>(i) * PX + ex<LP, DIM>(i);
+        const T dd = (phiS[rs(pm + em<LP, DIM>(i))][pc + o] - phiS[rs(pm - em<LP, DIM>(i))][pc - o]) / T(2);
+        if (LP::E[i][0] != 0) p0 += (T(LP::W[i]) * T(LP::E[i][0])) * dd;
+        if (LP::E[i][1] != 0) p1 += (T(LP::W[i]) * T(LP::E[i][1])) * dd;
+        if (LP::E[i][2] != 0) p2 += (T(LP::W[i]) * T(LP::E[i][2])) * dd;
       }
-      const int pc = (hy + PYO) * PX + (hx + 1);  // node in the phi ring
-      const T phc = phiS[pm & 3][pc];
-      // gradient of phi^n, lattice units
-      T p0 = T(0), p1 = T(0), p2 = T(0);
-      if (sd.grad_cd) {
-        p0 = (phiS[pm & 3][pc + 1] - phiS[pm & 3][pc - 1]) / T(2);
-        if constexpr (DIM == 3) {
-          p1 = (phiS[pm & 3][pc + PX] - phiS[pm & 3][pc - PX]) / T(2);
-          p2 = (phiS[(pm + 1) & 3][pc] - phiS[(pm - 1) & 3][pc]) / T(2);
-        } else {
-          p1 = (phiS[(pm + 1) & 3][pc] - phiS[(pm - 1) & 3][pc]) / T(2);
-        }
-      } else {
+      p0 *= T(LP::INV_E2);
+      p1 *= T(LP::INV_E2);
+      p2 *= T(LP::INV_E2);
+    }
+    // crystal index, Jacobi dilation by one node per step
+    int16_t idn = 0;
+    if constexpr (IDS) {
+      idn = idS[rs4(pm)][pc];
+      const T r2 = (p0 * p0 + p1 * p1) + p2 * p2;
+      if (idn == 0 && r2 > T(sd.xi2)) {
+        T best = T(-1e30);
+        int16_t bid = 0;
 #pragma unroll
         for (int i = 1; i < QP; ++i) {
           const int o = ey<LP, DIM>(i) * PX + ex<LP, DIM>(i);
-          const T dd = (phiS[(pm + em<LP, DIM>(i)) & 3][pc + o] - phiS[(pm - em<LP, DIM>(i)) & 3][pc - o]) / T(2);
-          if (LP::E[i][0] != 0) p0 += (T(LP::W[i]) * T(LP::E[i][0])) * dd;
-          if (LP::E[i][1] != 0) p1 += (T(LP::W[i]) * T(LP::E[i][1])) * dd;
-          if (LP::E[i][2] != 0) p2 += (T(LP::W[i]) * T(LP::E[i][2])) * dd;
-        }
-        p0 *= T(LP::INV_E2);
-        p1 *= T(LP::INV_E2);
-        p2 *= T(LP::INV_E2);
-      }
-      // crystal index, Jacobi dilation by one node per step
-      int16_t idn = 0;
-      if constexpr (IDS) {
-        idn = idS[pm & 3][pc];
-        const T r2 = (p0 * p0 + p1 * p1) + p2 * p2;
-        if (idn == 0 && r2 > T(sd.xi2)) {
-          T best = T(-1e300);
-          int16_t bid = 0;
-#pragma unroll
-          for (int i = 1; i < QP; ++i) {
-            const int o = ey<LP, DIM>(i) * PX + ex<LP, DIM>(i);
-            const int16_t nb = idS[(pm + em<LP, DIM>(i)) & 3][pc + o];
-            const T ph = phiS[(pm + em<LP, DIM>(i)) & 3][pc + o];
-            if (nb != 0 && (ph > best || (ph == best && nb < bid))) {
-              best = ph;
-              bid = nb;
-            }
+          const int16_t nb = idS[rs4(pm + em<LP, DIM>(i))][pc + o];
+          const T ph = phiS[rs(pm + em<LP, DIM>(i))][pc + o];
+          if (nb != 0 && (ph > best || (ph == best && nb < bid))) {
+            best = ph;
+            bid = nb;
           }
-          idn = bid;
         }
+        idn = bid;
       }
-      // u^n from the stored heat populations
-      T fd[QU];
-      T us_self;
-      const T un = gather_u<DIM, ST>(sd, gx, gy, gm, fd, us_self);
-      // a_s, N, relaxation and source
-      const AnisoDev *A = IDS ? (idn > 0 ? sd.aniso + idn : nullptr) : sd.aniso;
-      T a, Nx, Ny, Nz;
-      flux<T>(A, p0, p1, p2, a, Nx, Ny, Nz);
-      const T a2 = a * a;
-      const T om = T(1) / (a2 * T(sd.kphi) + T(0.5));
-      const T o1 = T(1) - phc * phc;
-      const T Qs = (phc - T(sd.lambda) * un * o1) * o1 * T(sd.s);
-      const T cC = -om * T(sd.kphi);
-      const int node = hy * HX + hx;
-      parS[ps][0][node] = T(1) - om;
-      parS[ps][1][node] = ST::OFF ? Qs : om * phc + Qs;
-      if constexpr (DIM == 3) {
-        parS[ps][2][node] = cC * Nx;
-        parS[ps][3][node] = cC * Ny;
-        parS[ps][4][node] = cC * Nz;
-      } else {
-        parS[ps][2][node] = cC * Nx;
-        parS[ps][3][node] = cC * Ny;  // the lattice y is the march axis in 2D
-      }
-      parS[ps][NP - 1][node] = T(1) / a2;
-      if (k == tid) {
+    }
+    // u^n = sum_i f_i^n(x), f_i^n(x) = f*_i(x - e_i) (prefetched in kv)
+    T fd[QU];
+    T us_self = T(0);
+    if constexpr (OFF) us_self = usS[rs4(pm)][pc];
+    T usum = T(0);
 #pragma unroll
-        for (int i = 0; i < QU; ++i) fd_nxt[i] = fd[i];
-        u_nxt = un;
-        us_nxt = us_self;
-        id_nxt = idn;
+    for (int i = 0; i < QU; ++i) {
+      const T kvv = T(kv[i]);
+      if constexpr (OFF) {
+        unsigned src;
+        int d, ox, oy, om;
+        heat_src(gx, gy, gm, i, src, d, ox, oy, om);
+        const float usrc = usS[rs4(pm + om)][pc + oy * PX + ox];
+        fd[i] = T(LU::W[i]) * (usrc - us_self) + kvv;
+      } else {
+        fd[i] = kvv;
       }
+      usum += fd[i];
+    }
+    const T un = OFF ? us_self + usum : usum;
+    // a_s, N, relaxation and source
+    const AnisoDev *A = IDS ? (idn > 0 ? sd.aniso + idn : nullptr) : sd.aniso;
+    T a, Nx, Ny, Nz;
+    flux<T>(A, p0, p1, p2, a, Nx, Ny, Nz);
+    const T a2 = a * a;
+    const T om_ = rcp(a2 * T(sd.kphi) + T(0.5));
+    const T o1 = T(1) - phc * phc;
+    const T Qs = (phc - T(sd.lambda) * un * o1) * o1 * T(sd.s);
+    const T cC = -om_ * T(sd.kphi);
+    const int node = hy * HX + hx;
+    parS[ps][0][node] = T(1) - om_;
+    parS[ps][1][node] = OFF ? Qs : om_ * phc + Qs;
+    parS[ps][2][node] = cC * Nx;
+    parS[ps][3][node] = cC * Ny;  // in 2D the lattice y is the march axis
+    if constexpr (DIM == 3) parS[ps][4][node] = cC * Nz;
+    parS[ps][NP - 1][node] = rcp(a2);
+    if (own_node) {
+#pragma unroll
+      for (int i = 0; i < QU; ++i) fd_nxt[i] = fd[i];
+      u_nxt = un;
+      us_nxt = us_self;
+      id_nxt = idn;
     }
   };
 
-  // component of C along direction i of the phi lattice (C stored as x, then
-  // the in-plane y in 3D, then the march axis)
+  // component of C along direction i of the phi lattice
   auto eC = [&](int i, int ps, int node) -> T {
     T v = T(0);
     if (LP::E[i][0] != 0) v += T(LP::E[i][0]) * parS[ps][2][node];
@@ -242,120 +396,171 @@ __global__ __launch_bounds__(64 * TY) void step_kernel(SimDev sd, TileDev tc) {
     return v;
   };
 
-  // ---- warm-up: phi planes m0-2 .. m0+1, coefficients of planes m0-1, m0 ----
-  for (int pm = m0 - 2; pm <= m0 + 1; ++pm) load_plane(pm);
-  __syncthreads();
+  const int gx_o = x0 + tx;
+  const int gy_o = y0 + ty;
+  const bool own = in_range(gx_o, sd.nx) && (DIM == 2 || in_range(gy_o, sd.nyp));
+  const int nodeo = hy_o * HX + hx_o;
+  const int pco = (hy_o + PYO) * PX + (hx_o + 1);
+
   int sp = 0, sc = 1, sn = 2;  // coefficient slots of planes m-1, m, m+1
-  compute_params(m0 - 1, sp);
-  compute_params(m0, sc);
+
+  // ---- B: write node y of plane m ---------------------------------------------
+  auto output = [&](int m, bool walls) {
+    const unsigned iy = lin(sd, gx_o, gy_o, m);
+    const unsigned iyb = iy * (unsigned)sizeof(S);
+    S gy_r[QP], gx_r[QP];
+    bool unk[QP];
+    // one batch of loads: g_i(y) and g_i(y - e_i)
+    if (xy_in1 && m >= 1 && m + 1 < sd.nm) {
+#pragma unroll
+      for (int i = 0; i < QP; ++i) {
+        unk[i] = false;
+        gy_r[i] = ldb(gfield(i), iyb);
+        gx_r[i] = ldb(gfield(i), iyb + boff_of(ex<LP, DIM>(i), ey<LP, DIM>(i), em<LP, DIM>(i), sizeof(S)));
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < QP; ++i) {
+        const int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
+        int sx = gx_o - cx, sy = gy_o - cy, sm = m - cm;
+        if (per) {
+          sx = wrapc(sx, sd.nx);
+          sy = (DIM == 3) ? wrapc(sy, sd.nyp) : 0;
+          sm = wrapc(sm, sd.nm);
+          unk[i] = false;
+        } else {
+          unk[i] = !(in_range(sx, sd.nx) && (DIM == 2 || in_range(sy, sd.nyp)) && in_range(sm, sd.nm));
+        }
+        const unsigned isrc = unk[i] ? iy : lin(sd, sx, sy, sm);
+        gy_r[i] = ldb(gfield(i), iyb);
+        gx_r[i] = ldb(gfield(i), isrc * (unsigned)sizeof(S));
+      }
+    }
+    const T phy = phiS[rs(m)][pco];
+    T d[QP];
+#pragma unroll
+    for (int i = 0; i < QP; ++i) {
+      const int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
+      const int ps = (cm == 1) ? sp : ((cm == -1) ? sn : sc);
+      const int node = nodeo - cy * HX - cx;
+      const T gy_ = ST::ld(&gy_r[i]);
+      const T gx_ = ST::ld(&gx_r[i]);
+      const T Acoef = parS[ps][0][node];
+      const T Bcoef = parS[ps][1][node];
+      const T ia2 = parS[ps][NP - 1][node];
+      const T src = T(LP::W[i]) * (Bcoef + eC(i, ps, node));
+      if constexpr (OFF) {
+        const T phx = phiS[rs(m - cm)][pco - cy * PX - cx];
+        const T hs = Acoef * gx_ + src;
+        d[i] = gy_ + ia2 * (T(LP::W[i]) * (phx - phy) + hs - gy_);
+      } else {
+        const T gs = Acoef * gx_ + src;
+        d[i] = gy_ + ia2 * (gs - gy_);
+      }
+    }
+    if (walls) {
+      // bounce-back: an unknown incoming population takes the opposite one; if
+      // that is unknown too, the local post-collision opposite population
+      T dn[QP];
+#pragma unroll
+      for (int i = 0; i < QP; ++i) {
+        const int j = LP::OPP[i];
+        const T loc = parS[sc][0][nodeo] * ST::ld(&gy_r[j]) + T(LP::W[j]) * (parS[sc][1][nodeo] + eC(j, sc, nodeo));
+        dn[i] = unk[i] ? (unk[j] ? loc : d[j]) : d[i];
+      }
+#pragma unroll
+      for (int i = 0; i < QP; ++i) d[i] = dn[i];
+    }
+    T sum = T(0);
+#pragma unroll
+    for (int i = 0; i < QP; ++i) sum += d[i];
+    const T phn = OFF ? phy + sum : sum;
+#pragma unroll
+    for (int i = 0; i < QP; ++i) {
+      const T v = OFF ? d[i] - T(LP::W[i]) * sum : d[i];
+      ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(gofield(i)) + iyb), v);
+    }
+    stb(Phout, iy * (unsigned)sizeof(PT), (PT)phn);
+
+    // heat equation at y: BGK toward w_i u^n with source (phi^{n+1} - phi^n)/2
+    const T half_dphi = T(0.5) * (phn - phy);
+    const T om_u = T(sd.omega_u);
+    if constexpr (OFF) {
+      const T Sm = u_cur - us_cur;  // sum of the decoded offsets
+      const T keep = T(1) - om_u;
+#pragma unroll
+      for (int i = 0; i < QU; ++i)
+        ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(i)) + iyb), keep * (fd_cur[i] - T(LU::W[i]) * Sm));
+      stb(sd.us_out, iy * 4u, float(u_cur + half_dphi));
+    } else {
+#pragma unroll
+      for (int i = 0; i < QU; ++i) {
+        const T fi = fd_cur[i];
+        ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(i)) + iyb),
+               fi - om_u * (fi - T(LU::W[i]) * u_cur) + T(LU::W[i]) * half_dphi);
+      }
+    }
+    if constexpr (IDS) stb(sd.id_out, iy * 2u, id_cur);
+  };
+
+  // planes whose pulls can meet a wall (only then is bounce-back applied)
+  const bool xy_walls = !per && !xy_in1;
+  auto walls_at = [&](int m) { return !per && (xy_walls || m == 0 || m == sd.nm - 1); };
+
+  // ---- warm-up ----------------------------------------------------------------
+  // ring planes m0-2 .. m0+1; coefficients of planes m0-1 and m0 (gathers
+  // loaded on the spot); then ring plane m0+2 and the gathers of plane m0+1
+  for (int pm = m0 - 2; pm <= m0 + 1; ++pm) {
+    ring_fetch(pm);
+    ring_commit(pm);
+  }
   __syncthreads();
+  for (int pm = m0 - 1; pm <= m0; ++pm) {
+    const int ps = (pm == m0) ? sc : sp;
+    gather_fetch(hx_o, hy_o, pm, kv_o_c);
+    if (has_h) gather_fetch(hx_h, hy_h, pm, kv_h_c);
+    param_node(hx_o, hy_o, pm, ps, kv_o_c, true);
+    if (has_h) param_node(hx_h, hy_h, pm, ps, kv_h_c, false);
+  }
+  __syncthreads();
+  ring_fetch(m0 + 2);
+  ring_commit(m0 + 2);
+  gather_fetch(hx_o, hy_o, m0 + 1, kv_o_c);
+  if (has_h) gather_fetch(hx_h, hy_h, m0 + 1, kv_h_c);
 #pragma unroll
   for (int i = 0; i < QU; ++i) fd_cur[i] = fd_nxt[i];
   u_cur = u_nxt;
   us_cur = us_nxt;
   id_cur = id_nxt;
-
-  const int gx = x0 + tx;
-  const int gy = y0 + ty;
-  const bool own = in_range(gx, sd.nx) && (DIM == 2 || in_range(gy, sd.nyp));
-  const int hxo = tx + 1, hyo = (DIM == 3) ? ty + 1 : 0;
-  const int nodeo = hyo * HX + hxo;
-  const int pco = (hyo + PYO) * PX + (hxo + 1);
+  __syncthreads();
 
   for (int m = m0; m < m1; ++m) {
-    load_plane(m + 2);
-    __syncthreads();
-    compute_params(m + 1, sn);
-    __syncthreads();
-
-    if (own) {
-      const long long iy = lin(sd, gx, gy, m);
-      const T phy = phiS[m & 3][pco];
-      T d[QP];
-      bool unk[QP];
-#pragma unroll
-      for (int i = 0; i < QP; ++i) {
-        const int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
-        int sx = gx - cx, sy = gy - cy, sm = m - cm;
-        unk[i] = false;
-        if (per) {
-          sx = wrapc(sx, sd.nx);
-          if (DIM == 3) sy = wrapc(sy, sd.nyp);
-          sm = wrapc(sm, sd.nm);
-        } else if (!in_range(sx, sd.nx) || (DIM == 3 && !in_range(sy, sd.nyp)) || !in_range(sm, sd.nm)) {
-          unk[i] = true;
-          d[i] = T(0);
-          continue;
-        }
-        const int ps = (cm == 1) ? sp : ((cm == -1) ? sn : sc);
-        const int node = nodeo - cy * HX - cx;
-        const T gy_ = ST::ld(Gin + (long long)i * sd.fstride + iy);
-        const T gx_ = ST::ld(Gin + (long long)i * sd.fstride + lin(sd, sx, sy, sm));
-        const T Acoef = parS[ps][0][node];
-        const T Bcoef = parS[ps][1][node];
-        const T ia2 = parS[ps][NP - 1][node];
-        const T src = T(LP::W[i]) * (Bcoef + eC(i, ps, node));
-        if constexpr (ST::OFF) {
-          const T phx = phiS[(m - cm) & 3][pco - cy * PX - cx];
-          const T hs = Acoef * gx_ + src;
-          d[i] = gy_ + ia2 * (T(LP::W[i]) * (phx - phy) + hs - gy_);
-        } else {
-          const T gs = Acoef * gx_ + src;
-          d[i] = gy_ + ia2 * (gs - gy_);
-        }
-      }
-      if (!per) {
-        // bounce-back: an unknown incoming population takes the opposite one;
-        // if that is unknown too, the local post-collision opposite population
-#pragma unroll
-        for (int i = 1; i < QP; ++i) {
-          if (!unk[i]) continue;
-          const int j = LP::OPP[i];
-          if (!unk[j]) {
-            d[i] = d[j];
-          } else {
-            const T gj = ST::ld(Gin + (long long)j * sd.fstride + iy);
-            d[i] = parS[sc][0][nodeo] * gj + T(LP::W[j]) * (parS[sc][1][nodeo] + eC(j, sc, nodeo));
-          }
-        }
-      }
-      T sum = T(0);
-#pragma unroll
-      for (int i = 0; i < QP; ++i) sum += d[i];
-      const T phn = ST::OFF ? phy + sum : sum;
-#pragma unroll
-      for (int i = 0; i < QP; ++i) {
-        const T v = ST::OFF ? d[i] - T(LP::W[i]) * sum : d[i];
-        ST::st(Gout + (long long)i * sd.fstride + iy, v);
-      }
-      Phout[iy] = (typename ST::P)phn;
-
-      // heat equation at y: BGK toward w_i u^n with source (phi^{n+1} - phi^n)/2
-      const T half_dphi = T(0.5) * (phn - phy);
-      const T om_u = T(sd.omega_u);
-      if constexpr (ST::OFF) {
-        const T Sm = u_cur - us_cur;  // sum of decoded offsets
-        const T keep = T(1) - om_u;
-#pragma unroll
-        for (int i = 0; i < QU; ++i) ST::st(Fout + (long long)i * sd.fstride + iy, keep * (fd_cur[i] - T(LU::W[i]) * Sm));
-        sd.us_out[iy] = float(u_cur + half_dphi);
-      } else {
-#pragma unroll
-        for (int i = 0; i < QU; ++i) {
-          const T fi = fd_cur[i];
-          ST::st(Fout + (long long)i * sd.fstride + iy, fi - om_u * (fi - T(LU::W[i]) * u_cur) + T(LU::W[i]) * half_dphi);
-        }
-      }
-      if constexpr (IDS) sd.id_out[iy] = id_cur;
+    // loads for the next iterations: ring plane m+3, gathers of plane m+2
+    const bool more_ring = m + 3 <= m1 + 1;
+    if (more_ring) ring_fetch(m + 3);
+    if (m + 2 <= m1) {
+      gather_fetch(hx_o, hy_o, m + 2, kv_o_n);
+      if (has_h) gather_fetch(hx_h, hy_h, m + 2, kv_h_n);
     }
+    // A: coefficients of plane m+1 (LDS and prefetched registers only)
+    param_node(hx_o, hy_o, m + 1, sn, kv_o_c, true);
+    if (has_h) param_node(hx_h, hy_h, m + 1, sn, kv_h_c, false);
     __syncthreads();
-    // rotate the coefficient ring and the own-column registers
+    // B: plane m
+    if (own) output(m, walls_at(m));
+    if (more_ring) ring_commit(m + 3);
+    __syncthreads();
+    // rotate the coefficient ring, the own-column state and the prefetches
     const int t = sp;
     sp = sc;
     sc = sn;
     sn = t;
 #pragma unroll
-    for (int i = 0; i < QU; ++i) fd_cur[i] = fd_nxt[i];
+    for (int i = 0; i < QU; ++i) {
+      fd_cur[i] = fd_nxt[i];
+      kv_o_c[i] = kv_o_n[i];
+      kv_h_c[i] = kv_h_n[i];
+    }
     u_cur = u_nxt;
     us_cur = us_nxt;
     id_cur = id_nxt;
@@ -376,7 +581,6 @@ static hipError_t launch_step_ty(const SimDev &sd, const TileDev &tc, hipStream_
     return launch_step_t<2, 1, ST, IDS>(sd, tc, st);
   } else {
     switch (tc.ty) {
-      case 2: return launch_step_t<3, 2, ST, IDS>(sd, tc, st);
       case 4: return launch_step_t<3, 4, ST, IDS>(sd, tc, st);
       case 8:
         if constexpr (!std::is_same<ST, StF64>::value) return launch_step_t<3, 8, ST, IDS>(sd, tc, st);
