@@ -28,8 +28,9 @@
  *     lattice-unit gradient.
  *   - Device memory: the caller allocates one workspace of
  *     lb_pf_workspace_bytes() bytes (256-byte aligned) and owns it; the library
- *     lays out every field inside it and allocates no device memory of its own.
- *     The workspace must outlive the handle.
+ *     lays out every field inside it and allocates no device memory of its own
+ *     (a batched handle also holds HIP graph objects, which the HIP runtime
+ *     manages).  The workspace must outlive the handle.
  *   - Streams: every call that takes a hip_stream enqueues its work on that
  *     stream (a hipStream_t, or NULL for the null stream) and returns without
  *     waiting, unless stated otherwise.
@@ -123,8 +124,10 @@ typedef struct {
 typedef struct lbpf_handle lbpf_handle;
 
 /* Bytes of device workspace needed for n_sims simulations (n_sims > 1 is the
- * batched ensemble: every config must be 2D and share lattice and storage).
- * Returns LBPF_ERR_ARG / LBPF_ERR_UNSTABLE for an invalid config. */
+ * batched ensemble: every config must be 2D, share the storage mode and use
+ * the index field in all or none; sizes, parameters, boundaries and gradient
+ * methods may differ).  Returns LBPF_ERR_ARG / LBPF_ERR_UNSTABLE for an invalid
+ * config, LBPF_ERR_UNSUPPORTED for an ensemble outside these rules. */
 int lb_pf_workspace_bytes(const lbpf_config *cfgs, int n_sims, size_t *bytes);
 
 /* Validates the configs, converts to lattice units (Eqs. ThermalDiffusivity,
@@ -136,7 +139,12 @@ int lb_pf_init(const lbpf_config *cfgs, int n_sims, void *dev_workspace, size_t 
                void *hip_stream, lbpf_handle **out);
 
 /* Enqueues n_steps coupled steps (phase field, then heat) for every
- * simulation of the handle.  One fused kernel launch per step. */
+ * simulation of the handle.  One fused kernel launch per step.  A batched
+ * handle advances all its simulations in one persistent launch per step over
+ * a work list of (simulation, 64-wide column, rows) items, replayed from HIP
+ * graphs of 1 and 8 steps that are captured, on a private stream, the first
+ * time they are needed (that call waits for the upload of the work list after
+ * a change of tile). */
 int lb_pf_step(lbpf_handle *h, int n_steps, void *hip_stream);
 
 /* Reductions of the current state in FP64 (sums, solid fraction, tip).
@@ -165,9 +173,11 @@ int lb_pf_save_state(lbpf_handle *h, void *dev_buf, size_t bytes, void *hip_stre
 int lb_pf_load_state(lbpf_handle *h, const void *dev_buf, size_t bytes, void *hip_stream);
 
 /* Tile shape of the step kernel: tile_y (4 or 8; 8 needs FP32 arithmetic) rows
- * of 64 nodes per work-group in 3D (1 in 2D), and `chunk` planes marched per work-group.  0 keeps the current
- * value.  lb_pf_autotune times the candidate shapes on hip_stream (advancing
- * the state by the steps it times) and keeps the fastest. */
+ * of 64 nodes per work-group in 3D (1 in 2D), and `chunk` planes marched per
+ * work-group (rows per work item, at least 8, for a batched handle).  0 keeps
+ * the current value.  lb_pf_autotune times the candidate shapes on hip_stream
+ * (advancing the state by the steps it runs: three times steps_per_trial per
+ * candidate) and keeps the fastest. */
 int lb_pf_set_tile(lbpf_handle *h, int tile_y, int chunk);
 int lb_pf_get_tile(const lbpf_handle *h, int *tile_y, int *chunk);
 int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream);
@@ -175,6 +185,9 @@ int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream);
 /* Number of simulations, nodes of simulation `sim`, step counter. */
 int lb_pf_info(const lbpf_handle *h, int sim, int64_t *nodes, int64_t *step, int *q_phi, int *q_u);
 
+/* Frees the handle (not the workspace).  Work enqueued on the handle must be
+ * complete, except for a batched handle, whose destruction waits for the
+ * device because its graphs may still run. */
 int lb_pf_destroy(lbpf_handle *h);
 const char *lb_pf_last_error(void);
 

@@ -50,12 +50,36 @@ struct SimHost {
 
 }  // namespace
 
+// Batched ensemble (2D, n_sims > 1): the per-simulation SimDev tables of both
+// parities and the work list live in the workspace; each step is one
+// persistent launch, replayed from HIP graphs captured once per parity.
+namespace {
+constexpr int kMinBatchChunk = 8;  // rows per work item, lower bound (sizes the work list)
+constexpr int kGraphSteps = 8;     // steps per long graph (even: the parity is restored)
+
+struct BatchState {
+  bool on = false;
+  bool ids = false;
+  int storage = 0;
+  int chunk = 32;
+  size_t off_sims = 0, off_items = 0;  // workspace offsets
+  int max_items = 0;
+  std::vector<SimDev> tables;          // [parity][sim]
+  std::vector<BatchItem> items;
+  int n_items = 0, grid = 0, blocks_per_cu = 0, n_cu = 0;
+  bool dirty = true;                   // tables / items not uploaded yet
+  hipStream_t cap = nullptr;           // private stream used only for capture
+  hipGraphExec_t exec[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [parity][one step, kGraphSteps]
+};
+}  // namespace
+
 struct lbpf_handle {
   std::vector<SimHost> sims;
   char *ws = nullptr;
   size_t bytes = 0;
   int parity = 0;
   int64_t step = 0;
+  BatchState batch;
 };
 
 namespace {
@@ -119,7 +143,7 @@ void default_tile(SimHost &s) {
   t.tiles_x = (s.nx + 63) / 64;
   t.tiles_y = s.dim == 3 ? (s.nyp + t.ty - 1) / t.ty : 1;
   const long long tiles = (long long)t.tiles_x * t.tiles_y;
-  const long long target = 8192;
+  const long long target = 16384;  // work-groups per launch: 16 x 1024 for 512^3
   long long ch = (s.nm * tiles + target - 1) / target;
   ch = std::max<long long>(ch, s.dim == 3 ? 16 : 16);
   ch = std::min<long long>(ch, s.nm);
@@ -246,6 +270,8 @@ int plan_all(const lbpf_config *cfgs, int n_sims, std::vector<SimHost> &sims, si
     if (n_sims > 1 && (cfgs[k].lattice != LBPF_D2Q9_D2Q5 || cfgs[k].lattice != cfgs[0].lattice ||
                        cfgs[k].storage != cfgs[0].storage))
       return fail(LBPF_ERR_UNSUPPORTED, "a batched ensemble must be 2D with one storage mode");
+    if (n_sims > 1 && (cfgs[k].use_ids != 0) != (cfgs[0].use_ids != 0))
+      return fail(LBPF_ERR_UNSUPPORTED, "a batched ensemble must use the index field in all or none of its configs");
     plan(cfgs[k], sims[k], cursor);
     sims[k].aniso.assign(cfgs[k].aniso, cfgs[k].aniso + cfgs[k].n_aniso);
     sims[k].seeds.assign(cfgs[k].seeds, cfgs[k].seeds + cfgs[k].n_seeds);
@@ -256,6 +282,46 @@ int plan_all(const lbpf_config *cfgs, int n_sims, std::vector<SimHost> &sims, si
   }
   total = align_up(cursor);
   return LBPF_OK;
+}
+
+// Workspace of the batched tables, after the simulations.
+void plan_batch(const std::vector<SimHost> &sims, BatchState &b, size_t &total) {
+  b = BatchState();
+  if (sims.size() < 2) return;
+  b.on = true;
+  b.ids = sims[0].cfg.use_ids != 0;
+  b.storage = sims[0].storage;
+  long long items = 0;
+  for (const SimHost &s : sims) items += (long long)((s.nx + 63) / 64) * ((s.nm + kMinBatchChunk - 1) / kMinBatchChunk);
+  b.max_items = (int)items;
+  b.off_sims = align_up(total);
+  total = align_up(b.off_sims + sizeof(SimDev) * 2 * sims.size());
+  b.off_items = total;
+  total = align_up(b.off_items + sizeof(BatchItem) * (size_t)b.max_items);
+}
+
+// Work list for `chunk` rows per item, in decreasing cost (rows plus the
+// three warm-up planes, times the columns in use); ties keep (sim, x0, m0)
+// order.  The order does not change results: items write disjoint nodes.
+void build_items(const std::vector<SimHost> &sims, BatchState &b) {
+  struct Keyed {
+    long long cost;
+    BatchItem it;
+  };
+  std::vector<Keyed> v;
+  for (size_t k = 0; k < sims.size(); ++k) {
+    const SimHost &s = sims[k];
+    for (int x0 = 0; x0 < s.nx; x0 += 64)
+      for (int m0 = 0; m0 < s.nm; m0 += b.chunk) {
+        const int m1 = std::min(m0 + b.chunk, s.nm);
+        v.push_back({(long long)(m1 - m0 + 3) * std::min(64, s.nx - x0), BatchItem{(int)k, x0, m0, m1}});
+      }
+  }
+  std::stable_sort(v.begin(), v.end(), [](const Keyed &a, const Keyed &c) { return a.cost > c.cost; });
+  b.items.resize(v.size());
+  for (size_t i = 0; i < v.size(); ++i) b.items[i] = v[i].it;
+  b.n_items = (int)v.size();
+  b.grid = std::max(1, std::min(b.n_items, b.blocks_per_cu * b.n_cu));
 }
 
 }  // namespace
@@ -280,6 +346,8 @@ int lb_pf_workspace_bytes(const lbpf_config *cfgs, int n_sims, size_t *bytes) {
   size_t total = 0;
   int rc = plan_all(cfgs, n_sims, sims, total);
   if (rc) return rc;
+  BatchState b;
+  plan_batch(sims, b, total);
   *bytes = total;
   return LBPF_OK;
 }
@@ -295,6 +363,7 @@ int lb_pf_init(const lbpf_config *cfgs, int n_sims, void *dev_workspace, size_t 
     delete h;
     return rc;
   }
+  plan_batch(h->sims, h->batch, total);
   if (!dev_workspace || (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign) != 0 || bytes < total) {
     delete h;
     return fail(LBPF_ERR_WORKSPACE, "workspace NULL, not 256-byte aligned, or smaller than lb_pf_workspace_bytes()");
@@ -337,14 +406,112 @@ int lb_pf_init(const lbpf_config *cfgs, int n_sims, void *dev_workspace, size_t 
       return fail(LBPF_ERR_HIP, std::string("initialisation failed: ") + hipGetErrorString(e));
     }
   }
+  if (h->batch.on) {
+    BatchState &b = h->batch;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&b.n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    b.blocks_per_cu = batch_blocks_per_cu(b.storage, b.ids);
+    if (e == hipSuccess && b.blocks_per_cu < 1) e = hipErrorInvalidDeviceFunction;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete h;
+      return fail(LBPF_ERR_HIP, std::string("batched set-up failed: ") + hipGetErrorString(e));
+    }
+    build_items(h->sims, b);
+  }
   *out = h;
   return LBPF_OK;
 }
+
+namespace {
+
+void drop_graphs(BatchState &b) {
+  for (auto &row : b.exec)
+    for (hipGraphExec_t &g : row)
+      if (g) {
+        hipGraphExecDestroy(g);
+        g = nullptr;
+      }
+}
+
+// Uploads the SimDev tables of both parities and the work list (then waits,
+// so that the host copies may change afterwards), and drops stale graphs.
+int batch_upload(lbpf_handle *h, hipStream_t st) {
+  BatchState &b = h->batch;
+  const size_t n = h->sims.size();
+  b.tables.resize(2 * n);
+  for (int p = 0; p < 2; ++p)
+    for (size_t k = 0; k < n; ++k) b.tables[p * n + k] = make_dev(h, h->sims[k], p);
+  HIPCHK(hipMemcpyAsync(h->ws + b.off_sims, b.tables.data(), sizeof(SimDev) * b.tables.size(),
+                        hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(h->ws + b.off_items, b.items.data(), sizeof(BatchItem) * b.items.size(),
+                        hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  drop_graphs(b);
+  b.dirty = false;
+  return LBPF_OK;
+}
+
+// Graph of `steps` consecutive batched steps starting from parity p.
+int batch_graph(lbpf_handle *h, int p, int kind) {
+  BatchState &b = h->batch;
+  if (b.exec[p][kind]) return LBPF_OK;
+  const int steps = kind == 0 ? 1 : kGraphSteps;
+  const SimDev *tab = reinterpret_cast<const SimDev *>(h->ws + b.off_sims);
+  const BatchItem *items = reinterpret_cast<const BatchItem *>(h->ws + b.off_items);
+  const size_t n = h->sims.size();
+  HIPCHK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int k = 0; k < steps && le == hipSuccess; ++k)
+    le = launch_batch(b.storage, b.ids, tab + ((p + k) & 1) * n, items, b.n_items, b.grid, b.cap);
+  hipGraph_t g = nullptr;
+  hipError_t ee = hipStreamEndCapture(b.cap, &g);
+  if (le != hipSuccess || ee != hipSuccess) {
+    if (g) hipGraphDestroy(g);
+    return fail(LBPF_ERR_HIP, std::string("graph capture failed: ") +
+                                  hipGetErrorString(le != hipSuccess ? le : ee));
+  }
+  hipError_t ie = hipGraphInstantiate(&b.exec[p][kind], g, nullptr, nullptr, 0);
+  hipGraphDestroy(g);
+  if (ie != hipSuccess) {
+    b.exec[p][kind] = nullptr;
+    return fail(LBPF_ERR_HIP, std::string("graph instantiation failed: ") + hipGetErrorString(ie));
+  }
+  return LBPF_OK;
+}
+
+int batch_step(lbpf_handle *h, int n_steps, hipStream_t st) {
+  BatchState &b = h->batch;
+  if (b.dirty) {
+    int rc = batch_upload(h, st);
+    if (rc) return rc;
+  }
+  int n = n_steps;
+  while (n >= kGraphSteps) {
+    int rc = batch_graph(h, h->parity, 1);
+    if (rc) return rc;
+    HIPCHK(hipGraphLaunch(b.exec[h->parity][1], st));
+    n -= kGraphSteps;
+    h->step += kGraphSteps;
+  }
+  for (; n > 0; --n) {
+    int rc = batch_graph(h, h->parity, 0);
+    if (rc) return rc;
+    HIPCHK(hipGraphLaunch(b.exec[h->parity][0], st));
+    h->parity ^= 1;
+    h->step++;
+  }
+  return LBPF_OK;
+}
+
+}  // namespace
 
 int lb_pf_step(lbpf_handle *h, int n_steps, void *hip_stream) {
   if (!h) return fail(LBPF_ERR_ARG, "null handle");
   if (n_steps < 0) return fail(LBPF_ERR_ARG, "n_steps < 0");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (h->batch.on) return batch_step(h, n_steps, st);
   for (int n = 0; n < n_steps; ++n) {
     for (const SimHost &s : h->sims) {
       const SimDev d = make_dev(h, s, h->parity);
@@ -467,6 +634,18 @@ int lb_pf_load_state(lbpf_handle *h, const void *dev_buf, size_t bytes, void *hi
 
 int lb_pf_set_tile(lbpf_handle *h, int tile_y, int chunk) {
   if (!h) return fail(LBPF_ERR_ARG, "null handle");
+  if (h->batch.on) {
+    if (tile_y > 1) return fail(LBPF_ERR_UNSUPPORTED, "2D tiles are one row high");
+    if (chunk > 0) {
+      if (chunk < kMinBatchChunk) return fail(LBPF_ERR_ARG, "batched work items need at least 8 rows");
+      if (chunk != h->batch.chunk) {
+        h->batch.chunk = chunk;
+        build_items(h->sims, h->batch);
+        h->batch.dirty = true;
+      }
+    }
+    return LBPF_OK;
+  }
   for (SimHost &s : h->sims) {
     int rc = set_tile(s, tile_y, chunk);
     if (rc) return rc;
@@ -477,7 +656,7 @@ int lb_pf_set_tile(lbpf_handle *h, int tile_y, int chunk) {
 int lb_pf_get_tile(const lbpf_handle *h, int *tile_y, int *chunk) {
   if (!h) return fail(LBPF_ERR_ARG, "null handle");
   if (tile_y) *tile_y = h->sims[0].tile.ty;
-  if (chunk) *chunk = h->sims[0].tile.chunk;
+  if (chunk) *chunk = h->batch.on ? h->batch.chunk : h->sims[0].tile.chunk;
   return LBPF_OK;
 }
 
@@ -492,12 +671,14 @@ int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream) {
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   float best = 1e30f;
-  int bty = s0.tile.ty, bch = s0.tile.chunk;
+  int bty = s0.tile.ty, bch = h->batch.on ? h->batch.chunk : s0.tile.chunk;
   for (int ty : tys) {
     if (s0.dim == 3 && ty == 8 && s0.storage == LBPF_FP64) continue;
     for (int ch : chunks) {
       if (lb_pf_set_tile(h, ty, ch)) continue;
-      int rc = lb_pf_step(h, 1, hip_stream);  // warm-up
+      // warm-up of twice the trial: the trial then starts from the same
+      // parity and finds every graph it replays already captured
+      int rc = lb_pf_step(h, 2 * steps_per_trial, hip_stream);
       if (rc) return rc;
       HIPCHK(hipEventRecord(e0, st));
       rc = lb_pf_step(h, steps_per_trial, hip_stream);
@@ -530,6 +711,14 @@ int lb_pf_info(const lbpf_handle *h, int sim, int64_t *nodes, int64_t *step, int
 }
 
 int lb_pf_destroy(lbpf_handle *h) {
+  if (!h) return LBPF_OK;
+  BatchState &b = h->batch;
+  if (b.cap) {
+    // graphs of this handle may still run on the caller's streams
+    hipDeviceSynchronize();
+    drop_graphs(b);
+    hipStreamDestroy(b.cap);
+  }
   delete h;
   return LBPF_OK;
 }

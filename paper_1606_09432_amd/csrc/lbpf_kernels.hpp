@@ -14,6 +14,12 @@ struct TileDev {
   int tiles_x, tiles_y, nchunks, chunk, ty;
 };
 
+// One item of a batched step: rows m0 .. m1-1 of the 64-wide column at x0
+// of simulation `sim` (2D).
+struct BatchItem {
+  int sim, x0, m0, m1;
+};
+
 // Seeds in lattice units, in (x, y, z) order.
 struct SeedDev {
   double x, y, z, r;
@@ -37,6 +43,11 @@ constexpr int kDiagVals = 6;
 constexpr int kDiagBlocks = 512;
 
 hipError_t launch_step(int dim, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st);
+// sims: the SimDev of every simulation for the step's parity (device memory).
+hipError_t launch_batch(int storage, bool ids, const SimDev *sims, const BatchItem *items, int n_items, int grid,
+                        hipStream_t st);
+// Resident work-groups per compute unit of the batch kernel (0 on failure).
+int batch_blocks_per_cu(int storage, bool ids);
 hipError_t launch_init(int dim, int storage, const SimDev &sd, int16_t *ids_out, const InitSrc &src,
                        hipStream_t st);
 hipError_t launch_diag(int dim, int storage, const SimDev &sd, double *partials, double *result,

@@ -1,6 +1,7 @@
 // Fused coupled step (phase field, then heat) for gfx950.
 //
-// One launch advances one simulation by one time step.  A work-group owns a
+// One launch advances one simulation (or, in 2D, a batch of them) by one time
+// step.  A work-group owns a
 // 64 x TY tile of the plane perpendicular to the march axis m (z in 3D, y in
 // 2D; TY = 1 in 2D) and walks `chunk` planes along m.  For output plane m it
 //   A. computes, for plane m+1 on the tile + 1-node halo, the gradient of
@@ -64,9 +65,16 @@ template <int DIM, int TY, class ST> constexpr int min_waves() {
   return DIM == 2 ? 4 : (std::is_same<ST, StF64>::value ? 2 : (TY == 8 ? 4 : 3));
 }
 
-template <int DIM, int TY, class ST, bool IDS>
+// BATCH = false: one simulation (sd_arg); the work-group id gives the tile and
+// the chunk of planes.  BATCH = true (2D): a persistent launch over the work
+// list `items` of a batched ensemble, whose per-simulation state is sims[k];
+// items are in decreasing cost and work-group b takes items b, b + G, b + 2G,
+// ... (G = grid size): static balance, no atomics, no per-step reset.
+template <int DIM, int TY, class ST, bool IDS, bool BATCH>
 __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(min_waves<DIM, TY, ST>(), 8))) void
-step_kernel(SimDev sd, TileDev tc) {
+step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const BatchItem *__restrict__ items,
+            int n_items) {
+  static_assert(!BATCH || DIM == 2, "batched ensembles are 2D");
   using T = typename ST::T;
   using LP = typename Lat<DIM>::P;
   using LU = typename Lat<DIM>::U;
@@ -91,479 +99,494 @@ step_kernel(SimDev sd, TileDev tc) {
   __shared__ int16_t idS[IDS ? 4 : 1][IDS ? PLANE_F : 1];
   __shared__ T parS[3][NP][PLANE_P];
 
-  const int tx = threadIdx.x;
-  const int ty = (DIM == 3) ? threadIdx.y : 0;
-  const int tid = ty * TX + tx;
+  for (int it = blockIdx.x; !BATCH || it < n_items; it += gridDim.x) {
+    const int tx = threadIdx.x;
+    const int ty = (DIM == 3) ? threadIdx.y : 0;
+    const int tid = ty * TX + tx;
 
-  int L = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile_x = L % tc.tiles_x;
-  L /= tc.tiles_x;
-  const int tile_y = L % tc.tiles_y;
-  const int chunk = L / tc.tiles_y;
-  const int x0 = tile_x * TX;
-  const int y0 = (DIM == 3) ? tile_y * TY : 0;
-  const int m0 = chunk * tc.chunk;
-  const int m1 = min(m0 + tc.chunk, sd.nm);
-  const int per = sd.periodic;
-  // tiles whose pulls (output: 1-node halo) or gathers (coefficients: 2-node
-  // halo) stay inside the box without wrapping: plain constant offsets there
-  const bool xy_in1 = x0 >= 1 && x0 + TX + 1 <= sd.nx && (DIM == 2 || (y0 >= 1 && y0 + TY + 1 <= sd.nyp));
-  const bool xy_in2 = x0 >= 2 && x0 + TX + 2 <= sd.nx && (DIM == 2 || (y0 >= 2 && y0 + TY + 2 <= sd.nyp));
-
-  // (no __restrict__: the g loads of B must stay below the barrier that ends A,
-  // where they would otherwise be hoisted and held in registers through A)
-  const S *Gin = reinterpret_cast<const S *>(sd.g_in);
-  S *Gout = reinterpret_cast<S *>(sd.g_out);
-  const S *Fin = reinterpret_cast<const S *>(sd.f_in);
-  S *Fout = reinterpret_cast<S *>(sd.f_out);
-  const PT *__restrict__ Phin = reinterpret_cast<const PT *>(sd.phi_in);
-  PT *__restrict__ Phout = reinterpret_cast<PT *>(sd.phi_out);
-  // per-direction field base pointers (uniform); node offsets are 32-bit
-  auto gfield = [&](int i) { return Gin + (size_t)i * (size_t)sd.fstride; };
-  auto gofield = [&](int i) { return Gout + (size_t)i * (size_t)sd.fstride; };
-  auto ffield = [&](int i) { return Fin + (size_t)i * (size_t)sd.fstride; };
-  auto fofield = [&](int i) { return Fout + (size_t)i * (size_t)sd.fstride; };
-  const int pitch = sd.pitch;
-  const int mstride = (int)sd.mstride;
-  // byte offset from a node to its neighbour -e (uniform)
-  auto boff_of = [&](int cx, int cy, int cm, int esize) { return -(cx + cy * pitch + cm * mstride) * esize; };
-
-  // ---- the coefficient nodes of this thread: its own column, maybe one halo node
-  const int hx_o = tx + 1, hy_o = (DIM == 3) ? ty + 1 : 0;
-  const bool has_h = tid < NHALO;
-  int hx_h = 0, hy_h = 0;
-  if constexpr (DIM == 3) {
-    const int r = tid;
-    if (r < HX) {
-      hx_h = r;
-      hy_h = 0;
-    } else if (r < 2 * HX) {
-      hx_h = r - HX;
-      hy_h = HY - 1;
-    } else if (r < 2 * HX + TY) {
-      hx_h = 0;
-      hy_h = r - 2 * HX + 1;
+    BatchItem bi{};
+    if constexpr (BATCH) bi = items[it];
+    const SimDev &sd = BATCH ? sims[bi.sim] : sd_arg;
+    int x0, y0, m0, m1;
+    if constexpr (BATCH) {
+      x0 = bi.x0;
+      y0 = 0;
+      m0 = bi.m0;
+      m1 = bi.m1;
+      __syncthreads();  // the previous item is done with the LDS rings
     } else {
-      hx_h = HX - 1;
-      hy_h = r - 2 * HX - TY + 1;
+      int L = xcd_remap(blockIdx.x, gridDim.x);
+      const int tile_x = L % tc.tiles_x;
+      L /= tc.tiles_x;
+      const int tile_y = L % tc.tiles_y;
+      const int chunk = L / tc.tiles_y;
+      x0 = tile_x * TX;
+      y0 = (DIM == 3) ? tile_y * TY : 0;
+      m0 = chunk * tc.chunk;
+      m1 = min(m0 + tc.chunk, sd.nm);
     }
-  } else {
-    hx_h = (tid == 0) ? 0 : HX - 1;
-  }
+    const int per = sd.periodic;
+    // tiles whose pulls (output: 1-node halo) or gathers (coefficients: 2-node
+    // halo) stay inside the box without wrapping: plain constant offsets there
+    const bool xy_in1 = x0 >= 1 && x0 + TX + 1 <= sd.nx && (DIM == 2 || (y0 >= 1 && y0 + TY + 1 <= sd.nyp));
+    const bool xy_in2 = x0 >= 2 && x0 + TX + 2 <= sd.nx && (DIM == 2 || (y0 >= 2 && y0 + TY + 2 <= sd.nyp));
 
-  // box coordinates of coefficient node (hx, hy) of plane pm; false when the
-  // node is never pulled from (outside the box, or beyond its one-node halo).
-  // The coordinates returned are always inside the box (clamped when invalid).
-  auto node_at = [&](int hx, int hy, int pm, int &gx, int &gy, int &gm) -> bool {
-    gx = x0 - 1 + hx;
-    gy = (DIM == 3) ? y0 - 1 + hy : 0;
-    gm = pm;
-    bool ok;
-    if (per) {
-      ok = gx <= sd.nx && (DIM == 2 || gy <= sd.nyp);
-      gx = wrapc(gx, sd.nx);
-      gy = (DIM == 3) ? wrapc(gy, sd.nyp) : 0;
-      gm = wrapc(gm, sd.nm);
-    } else {
-      ok = in_range(gx, sd.nx) && (DIM == 2 || in_range(gy, sd.nyp)) && in_range(gm, sd.nm);
-    }
-    gx = min(max(gx, 0), sd.nx - 1);
-    gy = (DIM == 3) ? min(max(gy, 0), sd.nyp - 1) : 0;
-    gm = min(max(gm, 0), sd.nm - 1);
-    return ok;
-  };
+    // (no __restrict__: the g loads of B must stay below the barrier that ends A,
+    // where they would otherwise be hoisted and held in registers through A)
+    const S *Gin = reinterpret_cast<const S *>(sd.g_in);
+    S *Gout = reinterpret_cast<S *>(sd.g_out);
+    const S *Fin = reinterpret_cast<const S *>(sd.f_in);
+    S *Fout = reinterpret_cast<S *>(sd.f_out);
+    const PT *__restrict__ Phin = reinterpret_cast<const PT *>(sd.phi_in);
+    PT *__restrict__ Phout = reinterpret_cast<PT *>(sd.phi_out);
+    // per-direction field base pointers (uniform); node offsets are 32-bit
+    auto gfield = [&](int i) { return Gin + (size_t)i * (size_t)sd.fstride; };
+    auto gofield = [&](int i) { return Gout + (size_t)i * (size_t)sd.fstride; };
+    auto ffield = [&](int i) { return Fin + (size_t)i * (size_t)sd.fstride; };
+    auto fofield = [&](int i) { return Fout + (size_t)i * (size_t)sd.fstride; };
+    const int pitch = sd.pitch;
+    const int mstride = (int)sd.mstride;
+    // byte offset from a node to its neighbour -e (uniform)
+    auto boff_of = [&](int cx, int cy, int cm, int esize) { return -(cx + cy * pitch + cm * mstride) * esize; };
 
-  // heat population i pulled by node (gx, gy, gm): stored field d at node src,
-  // which sits at ring offset (ox, oy, om) from the node.  Bounce-back for
-  // sources outside the box (Eq. Bounce-Back): the opposite population pulled
-  // from y + e_i, or the node's own post-collision opposite population.
-  auto heat_src = [&](int gx, int gy, int gm, int i, unsigned &src, int &d, int &ox, int &oy, int &om) {
-    const int cx = ex<LU, DIM>(i), cy = ey<LU, DIM>(i), cm = em<LU, DIM>(i);
-    int sx = gx - cx, sy = gy - cy, sm = gm - cm;
-    bool in1;
-    if (per) {
-      sx = wrapc(sx, sd.nx);
-      sy = (DIM == 3) ? wrapc(sy, sd.nyp) : 0;
-      sm = wrapc(sm, sd.nm);
-      in1 = true;
-    } else {
-      in1 = in_range(sx, sd.nx) && (DIM == 2 || in_range(sy, sd.nyp)) && in_range(sm, sd.nm);
-    }
-    const int tx_ = gx + cx, ty_ = gy + cy, tm_ = gm + cm;
-    const bool in2 = in_range(tx_, sd.nx) && (DIM == 2 || in_range(ty_, sd.nyp)) && in_range(tm_, sd.nm);
-    const int rx = in1 ? sx : (in2 ? tx_ : gx);
-    const int ry = in1 ? sy : (in2 ? ty_ : gy);
-    const int rm = in1 ? sm : (in2 ? tm_ : gm);
-    src = lin(sd, rx, ry, rm);
-    d = in1 ? i : LU::OPP[i];
-    ox = in1 ? -cx : (in2 ? cx : 0);
-    oy = in1 ? -cy : (in2 ? cy : 0);
-    om = in1 ? -cm : (in2 ? cm : 0);
-  };
-
-  // ---- ring staging: plane pm of phi^n, u*, I^n (tile + 2-node halo) --------
-  T ph_pf[NLOAD];
-  float us_pf[NLOAD];
-  int16_t id_pf[NLOAD];
-  // Halo coordinates beyond [-2, n + 1] (ragged last tile) are never read by a
-  // node that matters: they are clamped so every load stays in the box.  The
-  // FP64 form keeps the in-plane part of each ring entry (the same on every
-  // plane) in registers; the offset forms recompute it, which measures faster
-  // there (fewer live registers).
-  unsigned ring_off[NLOAD];
-  bool ring_out[NLOAD];
-  auto ring_xy = [&](int j, unsigned &off, bool &out) {
-    const int k = min(tid + j * NT, PLANE_F - 1);
-    const int px = k % PX, py = k / PX;
-    const int rx = min(max(x0 - 2 + px, -2), sd.nx + 1);
-    const int ry = (DIM == 3) ? min(max(y0 - 2 + py, -2), sd.nyp + 1) : 0;
-    const int gx = ghost(rx, sd.nx, per);
-    const int gy = (DIM == 3) ? ghost(ry, sd.nyp, per) : 0;
-    off = (unsigned)gy * (unsigned)pitch + (unsigned)gx;
-    out = !per && (!in_range(rx, sd.nx) || (DIM == 3 && !in_range(ry, sd.nyp)));
-  };
-  if constexpr (!OFF) {
-#pragma unroll
-    for (int j = 0; j < NLOAD; ++j) ring_xy(j, ring_off[j], ring_out[j]);
-  }
-  auto ring_fetch = [&](int pm) {
-    const int gm = ghost(pm, sd.nm, per);  // pm is always within [-2, nm + 1]
-    const bool mout = !per && !in_range(pm, sd.nm);
-    const unsigned mo = (unsigned)gm * (unsigned)mstride;
-#pragma unroll
-    for (int j = 0; j < NLOAD; ++j) {
-      if (tid + j * NT >= PLANE_F) break;
-      unsigned off;
-      bool out;
-      if constexpr (!OFF) {
-        off = ring_off[j];
-        out = ring_out[j];
+    // ---- the coefficient nodes of this thread: its own column, maybe one halo node
+    const int hx_o = tx + 1, hy_o = (DIM == 3) ? ty + 1 : 0;
+    const bool has_h = tid < NHALO;
+    int hx_h = 0, hy_h = 0;
+    if constexpr (DIM == 3) {
+      const int r = tid;
+      if (r < HX) {
+        hx_h = r;
+        hy_h = 0;
+      } else if (r < 2 * HX) {
+        hx_h = r - HX;
+        hy_h = HY - 1;
+      } else if (r < 2 * HX + TY) {
+        hx_h = 0;
+        hy_h = r - 2 * HX + 1;
       } else {
-        ring_xy(j, off, out);
+        hx_h = HX - 1;
+        hy_h = r - 2 * HX - TY + 1;
       }
-      const unsigned idx = mo + off;
-      ph_pf[j] = T(ldb(Phin, idx * (unsigned)sizeof(PT)));
-      if constexpr (OFF) us_pf[j] = ldb(sd.us_in, idx * 4u);
-      if constexpr (IDS) id_pf[j] = (mout || out) ? int16_t(0) : ldb(sd.id_in, idx * 2u);
-    }
-  };
-  // phi keeps 5 planes (B of plane m reads plane m-1 while plane m+3 is
-  // committed); u* and I^n, read in A only, keep 4
-  auto rs = [](int pm) { return (pm + 10) % 5; };
-  auto rs4 = [](int pm) { return (pm + 8) & 3; };
-  auto ring_commit = [&](int pm) {
-    const int slot = rs(pm), slot4 = rs4(pm);
-#pragma unroll
-    for (int j = 0; j < NLOAD; ++j) {
-      const int k = tid + j * NT;
-      if (k >= PLANE_F) break;
-      phiS[slot][k] = ph_pf[j];
-      if constexpr (OFF) usS[slot4][k] = us_pf[j];
-      if constexpr (IDS) idS[slot4][k] = id_pf[j];
-    }
-  };
-
-  // ---- heat populations gathered by a coefficient node (prefetched) ---------
-  S kv_o_c[QU], kv_h_c[QU], kv_o_n[QU], kv_h_n[QU];
-  auto gather_fetch = [&](int hx, int hy, int pm, S(&kv)[QU]) {
-    int gx, gy, gm;
-    node_at(hx, hy, pm, gx, gy, gm);
-    if (xy_in2 && pm >= 1 && pm + 1 < sd.nm) {
-      const unsigned ib = lin(sd, gx, gy, gm) * (unsigned)sizeof(S);
-#pragma unroll
-      for (int i = 0; i < QU; ++i)
-        kv[i] = ldb(ffield(i), ib + boff_of(ex<LU, DIM>(i), ey<LU, DIM>(i), em<LU, DIM>(i), sizeof(S)));
     } else {
-#pragma unroll
-      for (int i = 0; i < QU; ++i) {
-        unsigned src;
-        int d, ox, oy, om;
-        heat_src(gx, gy, gm, i, src, d, ox, oy, om);
-        kv[i] = ldb(ffield(d), src * (unsigned)sizeof(S));
-      }
+      hx_h = (tid == 0) ? 0 : HX - 1;
     }
-  };
 
-  // own-column node of the plane being prepared (nxt) and written (cur)
-  T fd_cur[QU], fd_nxt[QU];
-  T u_cur = T(0), u_nxt = T(0), us_cur = T(0), us_nxt = T(0);
-  int16_t id_cur = 0, id_nxt = 0;
-
-  // ---- A: coefficients of node (hx, hy) of plane pm into coefficient slot ps
-  auto param_node = [&](int hx, int hy, int pm, int ps, const S(&kv)[QU], bool own_node) {
-    int gx, gy, gm;
-    if (!node_at(hx, hy, pm, gx, gy, gm)) return;
-    const int pc = (hy + PYO) * PX + (hx + 1);  // node in the ring
-    const int sl0 = rs(pm);
-    const T phc = phiS[sl0][pc];
-    // gradient of phi^n, lattice units
-    T p0 = T(0), p1 = T(0), p2 = T(0);
-    if (sd.grad_cd) {
-      p0 = (phiS[sl0][pc + 1] - phiS[sl0][pc - 1]) / T(2);
-      if constexpr (DIM == 3) {
-        p1 = (phiS[sl0][pc + PX] - phiS[sl0][pc - PX]) / T(2);
-        p2 = (phiS[rs(pm + 1)][pc] - phiS[rs(pm - 1)][pc]) / T(2);
+    // box coordinates of coefficient node (hx, hy) of plane pm; false when the
+    // node is never pulled from (outside the box, or beyond its one-node halo).
+    // The coordinates returned are always inside the box (clamped when invalid).
+    auto node_at = [&](int hx, int hy, int pm, int &gx, int &gy, int &gm) -> bool {
+      gx = x0 - 1 + hx;
+      gy = (DIM == 3) ? y0 - 1 + hy : 0;
+      gm = pm;
+      bool ok;
+      if (per) {
+        ok = gx <= sd.nx && (DIM == 2 || gy <= sd.nyp);
+        gx = wrapc(gx, sd.nx);
+        gy = (DIM == 3) ? wrapc(gy, sd.nyp) : 0;
+        gm = wrapc(gm, sd.nm);
       } else {
-        p1 = (phiS[rs(pm + 1)][pc] - phiS[rs(pm - 1)][pc]) / T(2);
+        ok = in_range(gx, sd.nx) && (DIM == 2 || in_range(gy, sd.nyp)) && in_range(gm, sd.nm);
       }
-    } else {
-#pragma unroll
-      for (int i = 1; i < QP; ++i) {
-        const int o = ey<LP, DIM>(i) * PX + ex<LP, DIM>(i);
-        const T dd = (phiS[rs(pm + em<LP, DIM>(i))][pc + o] - phiS[rs(pm - em<LP, DIM>(i))][pc - o]) / T(2);
-        if (LP::E[i][0] != 0) p0 += (T(LP::W[i]) * T(LP::E[i][0])) * dd;
-        if (LP::E[i][1] != 0) p1 += (T(LP::W[i]) * T(LP::E[i][1])) * dd;
-        if (LP::E[i][2] != 0) p2 += (T(LP::W[i]) * T(LP::E[i][2])) * dd;
+      gx = min(max(gx, 0), sd.nx - 1);
+      gy = (DIM == 3) ? min(max(gy, 0), sd.nyp - 1) : 0;
+      gm = min(max(gm, 0), sd.nm - 1);
+      return ok;
+    };
+
+    // heat population i pulled by node (gx, gy, gm): stored field d at node src,
+    // which sits at ring offset (ox, oy, om) from the node.  Bounce-back for
+    // sources outside the box (Eq. Bounce-Back): the opposite population pulled
+    // from y + e_i, or the node's own post-collision opposite population.
+    auto heat_src = [&](int gx, int gy, int gm, int i, unsigned &src, int &d, int &ox, int &oy, int &om) {
+      const int cx = ex<LU, DIM>(i), cy = ey<LU, DIM>(i), cm = em<LU, DIM>(i);
+      int sx = gx - cx, sy = gy - cy, sm = gm - cm;
+      bool in1;
+      if (per) {
+        sx = wrapc(sx, sd.nx);
+        sy = (DIM == 3) ? wrapc(sy, sd.nyp) : 0;
+        sm = wrapc(sm, sd.nm);
+        in1 = true;
+      } else {
+        in1 = in_range(sx, sd.nx) && (DIM == 2 || in_range(sy, sd.nyp)) && in_range(sm, sd.nm);
       }
-      p0 *= T(LP::INV_E2);
-      p1 *= T(LP::INV_E2);
-      p2 *= T(LP::INV_E2);
+      const int tx_ = gx + cx, ty_ = gy + cy, tm_ = gm + cm;
+      const bool in2 = in_range(tx_, sd.nx) && (DIM == 2 || in_range(ty_, sd.nyp)) && in_range(tm_, sd.nm);
+      const int rx = in1 ? sx : (in2 ? tx_ : gx);
+      const int ry = in1 ? sy : (in2 ? ty_ : gy);
+      const int rm = in1 ? sm : (in2 ? tm_ : gm);
+      src = lin(sd, rx, ry, rm);
+      d = in1 ? i : LU::OPP[i];
+      ox = in1 ? -cx : (in2 ? cx : 0);
+      oy = in1 ? -cy : (in2 ? cy : 0);
+      om = in1 ? -cm : (in2 ? cm : 0);
+    };
+
+    // ---- ring staging: plane pm of phi^n, u*, I^n (tile + 2-node halo) --------
+    T ph_pf[NLOAD];
+    float us_pf[NLOAD];
+    int16_t id_pf[NLOAD];
+    // Halo coordinates beyond [-2, n + 1] (ragged last tile) are never read by a
+    // node that matters: they are clamped so every load stays in the box.  The
+    // FP64 form keeps the in-plane part of each ring entry (the same on every
+    // plane) in registers; the offset forms recompute it, which measures faster
+    // there (fewer live registers).
+    unsigned ring_off[NLOAD];
+    bool ring_out[NLOAD];
+    auto ring_xy = [&](int j, unsigned &off, bool &out) {
+      const int k = min(tid + j * NT, PLANE_F - 1);
+      const int px = k % PX, py = k / PX;
+      const int rx = min(max(x0 - 2 + px, -2), sd.nx + 1);
+      const int ry = (DIM == 3) ? min(max(y0 - 2 + py, -2), sd.nyp + 1) : 0;
+      const int gx = ghost(rx, sd.nx, per);
+      const int gy = (DIM == 3) ? ghost(ry, sd.nyp, per) : 0;
+      off = (unsigned)gy * (unsigned)pitch + (unsigned)gx;
+      out = !per && (!in_range(rx, sd.nx) || (DIM == 3 && !in_range(ry, sd.nyp)));
+    };
+    if constexpr (!OFF) {
+  #pragma unroll
+      for (int j = 0; j < NLOAD; ++j) ring_xy(j, ring_off[j], ring_out[j]);
     }
-    // crystal index, Jacobi dilation by one node per step
-    int16_t idn = 0;
-    if constexpr (IDS) {
-      idn = idS[rs4(pm)][pc];
-      const T r2 = (p0 * p0 + p1 * p1) + p2 * p2;
-      if (idn == 0 && r2 > T(sd.xi2)) {
-        T best = T(-1e30);
-        int16_t bid = 0;
-#pragma unroll
+    auto ring_fetch = [&](int pm) {
+      const int gm = ghost(pm, sd.nm, per);  // pm is always within [-2, nm + 1]
+      const bool mout = !per && !in_range(pm, sd.nm);
+      const unsigned mo = (unsigned)gm * (unsigned)mstride;
+  #pragma unroll
+      for (int j = 0; j < NLOAD; ++j) {
+        if (tid + j * NT >= PLANE_F) break;
+        unsigned off;
+        bool out;
+        if constexpr (!OFF) {
+          off = ring_off[j];
+          out = ring_out[j];
+        } else {
+          ring_xy(j, off, out);
+        }
+        const unsigned idx = mo + off;
+        ph_pf[j] = T(ldb(Phin, idx * (unsigned)sizeof(PT)));
+        if constexpr (OFF) us_pf[j] = ldb(sd.us_in, idx * 4u);
+        if constexpr (IDS) id_pf[j] = (mout || out) ? int16_t(0) : ldb(sd.id_in, idx * 2u);
+      }
+    };
+    // phi keeps 5 planes (B of plane m reads plane m-1 while plane m+3 is
+    // committed); u* and I^n, read in A only, keep 4
+    auto rs = [](int pm) { return (pm + 10) % 5; };
+    auto rs4 = [](int pm) { return (pm + 8) & 3; };
+    auto ring_commit = [&](int pm) {
+      const int slot = rs(pm), slot4 = rs4(pm);
+  #pragma unroll
+      for (int j = 0; j < NLOAD; ++j) {
+        const int k = tid + j * NT;
+        if (k >= PLANE_F) break;
+        phiS[slot][k] = ph_pf[j];
+        if constexpr (OFF) usS[slot4][k] = us_pf[j];
+        if constexpr (IDS) idS[slot4][k] = id_pf[j];
+      }
+    };
+
+    // ---- heat populations gathered by a coefficient node (prefetched) ---------
+    S kv_o_c[QU], kv_h_c[QU], kv_o_n[QU], kv_h_n[QU];
+    auto gather_fetch = [&](int hx, int hy, int pm, S(&kv)[QU]) {
+      int gx, gy, gm;
+      node_at(hx, hy, pm, gx, gy, gm);
+      if (xy_in2 && pm >= 1 && pm + 1 < sd.nm) {
+        const unsigned ib = lin(sd, gx, gy, gm) * (unsigned)sizeof(S);
+  #pragma unroll
+        for (int i = 0; i < QU; ++i)
+          kv[i] = ldb(ffield(i), ib + boff_of(ex<LU, DIM>(i), ey<LU, DIM>(i), em<LU, DIM>(i), sizeof(S)));
+      } else {
+  #pragma unroll
+        for (int i = 0; i < QU; ++i) {
+          unsigned src;
+          int d, ox, oy, om;
+          heat_src(gx, gy, gm, i, src, d, ox, oy, om);
+          kv[i] = ldb(ffield(d), src * (unsigned)sizeof(S));
+        }
+      }
+    };
+
+    // own-column node of the plane being prepared (nxt) and written (cur)
+    T fd_cur[QU], fd_nxt[QU];
+    T u_cur = T(0), u_nxt = T(0), us_cur = T(0), us_nxt = T(0);
+    int16_t id_cur = 0, id_nxt = 0;
+
+    // ---- A: coefficients of node (hx, hy) of plane pm into coefficient slot ps
+    auto param_node = [&](int hx, int hy, int pm, int ps, const S(&kv)[QU], bool own_node) {
+      int gx, gy, gm;
+      if (!node_at(hx, hy, pm, gx, gy, gm)) return;
+      const int pc = (hy + PYO) * PX + (hx + 1);  // node in the ring
+      const int sl0 = rs(pm);
+      const T phc = phiS[sl0][pc];
+      // gradient of phi^n, lattice units
+      T p0 = T(0), p1 = T(0), p2 = T(0);
+      if (sd.grad_cd) {
+        p0 = (phiS[sl0][pc + 1] - phiS[sl0][pc - 1]) / T(2);
+        if constexpr (DIM == 3) {
+          p1 = (phiS[sl0][pc + PX] - phiS[sl0][pc - PX]) / T(2);
+          p2 = (phiS[rs(pm + 1)][pc] - phiS[rs(pm - 1)][pc]) / T(2);
+        } else {
+          p1 = (phiS[rs(pm + 1)][pc] - phiS[rs(pm - 1)][pc]) / T(2);
+        }
+      } else {
+  #pragma unroll
         for (int i = 1; i < QP; ++i) {
           const int o = ey<LP, DIM>(i) * PX + ex<LP, DIM>(i);
-          const int16_t nb = idS[rs4(pm + em<LP, DIM>(i))][pc + o];
-          const T ph = phiS[rs(pm + em<LP, DIM>(i))][pc + o];
-          if (nb != 0 && (ph > best || (ph == best && nb < bid))) {
-            best = ph;
-            bid = nb;
-          }
+          const T dd = (phiS[rs(pm + em<LP, DIM>(i))][pc + o] - phiS[rs(pm - em<LP, DIM>(i))][pc - o]) / T(2);
+          if (LP::E[i][0] != 0) p0 += (T(LP::W[i]) * T(LP::E[i][0])) * dd;
+          if (LP::E[i][1] != 0) p1 += (T(LP::W[i]) * T(LP::E[i][1])) * dd;
+          if (LP::E[i][2] != 0) p2 += (T(LP::W[i]) * T(LP::E[i][2])) * dd;
         }
-        idn = bid;
+        p0 *= T(LP::INV_E2);
+        p1 *= T(LP::INV_E2);
+        p2 *= T(LP::INV_E2);
       }
-    }
-    // u^n = sum_i f_i^n(x), f_i^n(x) = f*_i(x - e_i) (prefetched in kv)
-    T fd[QU];
-    T us_self = T(0);
-    if constexpr (OFF) us_self = usS[rs4(pm)][pc];
-    T usum = T(0);
-#pragma unroll
-    for (int i = 0; i < QU; ++i) {
-      const T kvv = T(kv[i]);
-      if constexpr (OFF) {
-        unsigned src;
-        int d, ox, oy, om;
-        heat_src(gx, gy, gm, i, src, d, ox, oy, om);
-        const float usrc = usS[rs4(pm + om)][pc + oy * PX + ox];
-        fd[i] = T(LU::W[i]) * (usrc - us_self) + kvv;
+      // crystal index, Jacobi dilation by one node per step
+      int16_t idn = 0;
+      if constexpr (IDS) {
+        idn = idS[rs4(pm)][pc];
+        const T r2 = (p0 * p0 + p1 * p1) + p2 * p2;
+        if (idn == 0 && r2 > T(sd.xi2)) {
+          T best = T(-1e30);
+          int16_t bid = 0;
+  #pragma unroll
+          for (int i = 1; i < QP; ++i) {
+            const int o = ey<LP, DIM>(i) * PX + ex<LP, DIM>(i);
+            const int16_t nb = idS[rs4(pm + em<LP, DIM>(i))][pc + o];
+            const T ph = phiS[rs(pm + em<LP, DIM>(i))][pc + o];
+            if (nb != 0 && (ph > best || (ph == best && nb < bid))) {
+              best = ph;
+              bid = nb;
+            }
+          }
+          idn = bid;
+        }
+      }
+      // u^n = sum_i f_i^n(x), f_i^n(x) = f*_i(x - e_i) (prefetched in kv)
+      T fd[QU];
+      T us_self = T(0);
+      if constexpr (OFF) us_self = usS[rs4(pm)][pc];
+      T usum = T(0);
+  #pragma unroll
+      for (int i = 0; i < QU; ++i) {
+        const T kvv = T(kv[i]);
+        if constexpr (OFF) {
+          unsigned src;
+          int d, ox, oy, om;
+          heat_src(gx, gy, gm, i, src, d, ox, oy, om);
+          const float usrc = usS[rs4(pm + om)][pc + oy * PX + ox];
+          fd[i] = T(LU::W[i]) * (usrc - us_self) + kvv;
+        } else {
+          fd[i] = kvv;
+        }
+        usum += fd[i];
+      }
+      const T un = OFF ? us_self + usum : usum;
+      // a_s, N, relaxation and source
+      const AnisoDev *A = IDS ? (idn > 0 ? sd.aniso + idn : nullptr) : sd.aniso;
+      T a, Nx, Ny, Nz;
+      flux<T>(A, p0, p1, p2, a, Nx, Ny, Nz);
+      const T a2 = a * a;
+      const T om_ = rcp(a2 * T(sd.kphi) + T(0.5));
+      const T o1 = T(1) - phc * phc;
+      const T Qs = (phc - T(sd.lambda) * un * o1) * o1 * T(sd.s);
+      const T cC = -om_ * T(sd.kphi);
+      const int node = hy * HX + hx;
+      parS[ps][0][node] = T(1) - om_;
+      parS[ps][1][node] = OFF ? Qs : om_ * phc + Qs;
+      parS[ps][2][node] = cC * Nx;
+      parS[ps][3][node] = cC * Ny;  // in 2D the lattice y is the march axis
+      if constexpr (DIM == 3) parS[ps][4][node] = cC * Nz;
+      parS[ps][NP - 1][node] = rcp(a2);
+      if (own_node) {
+  #pragma unroll
+        for (int i = 0; i < QU; ++i) fd_nxt[i] = fd[i];
+        u_nxt = un;
+        us_nxt = us_self;
+        id_nxt = idn;
+      }
+    };
+
+    // component of C along direction i of the phi lattice
+    auto eC = [&](int i, int ps, int node) -> T {
+      T v = T(0);
+      if (LP::E[i][0] != 0) v += T(LP::E[i][0]) * parS[ps][2][node];
+      if (LP::E[i][1] != 0) v += T(LP::E[i][1]) * parS[ps][3][node];
+      if constexpr (DIM == 3) {
+        if (LP::E[i][2] != 0) v += T(LP::E[i][2]) * parS[ps][4][node];
+      }
+      return v;
+    };
+
+    const int gx_o = x0 + tx;
+    const int gy_o = y0 + ty;
+    const bool own = in_range(gx_o, sd.nx) && (DIM == 2 || in_range(gy_o, sd.nyp));
+    const int nodeo = hy_o * HX + hx_o;
+    const int pco = (hy_o + PYO) * PX + (hx_o + 1);
+
+    int sp = 0, sc = 1, sn = 2;  // coefficient slots of planes m-1, m, m+1
+
+    // ---- B: write node y of plane m ---------------------------------------------
+    auto output = [&](int m, bool walls) {
+      const unsigned iy = lin(sd, gx_o, gy_o, m);
+      const unsigned iyb = iy * (unsigned)sizeof(S);
+      S gy_r[QP], gx_r[QP];
+      bool unk[QP];
+      // one batch of loads: g_i(y) and g_i(y - e_i)
+      if (xy_in1 && m >= 1 && m + 1 < sd.nm) {
+  #pragma unroll
+        for (int i = 0; i < QP; ++i) {
+          unk[i] = false;
+          gy_r[i] = ldb(gfield(i), iyb);
+          gx_r[i] = ldb(gfield(i), iyb + boff_of(ex<LP, DIM>(i), ey<LP, DIM>(i), em<LP, DIM>(i), sizeof(S)));
+        }
       } else {
-        fd[i] = kvv;
+  #pragma unroll
+        for (int i = 0; i < QP; ++i) {
+          const int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
+          int sx = gx_o - cx, sy = gy_o - cy, sm = m - cm;
+          if (per) {
+            sx = wrapc(sx, sd.nx);
+            sy = (DIM == 3) ? wrapc(sy, sd.nyp) : 0;
+            sm = wrapc(sm, sd.nm);
+            unk[i] = false;
+          } else {
+            unk[i] = !(in_range(sx, sd.nx) && (DIM == 2 || in_range(sy, sd.nyp)) && in_range(sm, sd.nm));
+          }
+          const unsigned isrc = unk[i] ? iy : lin(sd, sx, sy, sm);
+          gy_r[i] = ldb(gfield(i), iyb);
+          gx_r[i] = ldb(gfield(i), isrc * (unsigned)sizeof(S));
+        }
       }
-      usum += fd[i];
-    }
-    const T un = OFF ? us_self + usum : usum;
-    // a_s, N, relaxation and source
-    const AnisoDev *A = IDS ? (idn > 0 ? sd.aniso + idn : nullptr) : sd.aniso;
-    T a, Nx, Ny, Nz;
-    flux<T>(A, p0, p1, p2, a, Nx, Ny, Nz);
-    const T a2 = a * a;
-    const T om_ = rcp(a2 * T(sd.kphi) + T(0.5));
-    const T o1 = T(1) - phc * phc;
-    const T Qs = (phc - T(sd.lambda) * un * o1) * o1 * T(sd.s);
-    const T cC = -om_ * T(sd.kphi);
-    const int node = hy * HX + hx;
-    parS[ps][0][node] = T(1) - om_;
-    parS[ps][1][node] = OFF ? Qs : om_ * phc + Qs;
-    parS[ps][2][node] = cC * Nx;
-    parS[ps][3][node] = cC * Ny;  // in 2D the lattice y is the march axis
-    if constexpr (DIM == 3) parS[ps][4][node] = cC * Nz;
-    parS[ps][NP - 1][node] = rcp(a2);
-    if (own_node) {
-#pragma unroll
-      for (int i = 0; i < QU; ++i) fd_nxt[i] = fd[i];
-      u_nxt = un;
-      us_nxt = us_self;
-      id_nxt = idn;
-    }
-  };
-
-  // component of C along direction i of the phi lattice
-  auto eC = [&](int i, int ps, int node) -> T {
-    T v = T(0);
-    if (LP::E[i][0] != 0) v += T(LP::E[i][0]) * parS[ps][2][node];
-    if (LP::E[i][1] != 0) v += T(LP::E[i][1]) * parS[ps][3][node];
-    if constexpr (DIM == 3) {
-      if (LP::E[i][2] != 0) v += T(LP::E[i][2]) * parS[ps][4][node];
-    }
-    return v;
-  };
-
-  const int gx_o = x0 + tx;
-  const int gy_o = y0 + ty;
-  const bool own = in_range(gx_o, sd.nx) && (DIM == 2 || in_range(gy_o, sd.nyp));
-  const int nodeo = hy_o * HX + hx_o;
-  const int pco = (hy_o + PYO) * PX + (hx_o + 1);
-
-  int sp = 0, sc = 1, sn = 2;  // coefficient slots of planes m-1, m, m+1
-
-  // ---- B: write node y of plane m ---------------------------------------------
-  auto output = [&](int m, bool walls) {
-    const unsigned iy = lin(sd, gx_o, gy_o, m);
-    const unsigned iyb = iy * (unsigned)sizeof(S);
-    S gy_r[QP], gx_r[QP];
-    bool unk[QP];
-    // one batch of loads: g_i(y) and g_i(y - e_i)
-    if (xy_in1 && m >= 1 && m + 1 < sd.nm) {
-#pragma unroll
-      for (int i = 0; i < QP; ++i) {
-        unk[i] = false;
-        gy_r[i] = ldb(gfield(i), iyb);
-        gx_r[i] = ldb(gfield(i), iyb + boff_of(ex<LP, DIM>(i), ey<LP, DIM>(i), em<LP, DIM>(i), sizeof(S)));
-      }
-    } else {
-#pragma unroll
+      const T phy = phiS[rs(m)][pco];
+      T d[QP];
+  #pragma unroll
       for (int i = 0; i < QP; ++i) {
         const int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
-        int sx = gx_o - cx, sy = gy_o - cy, sm = m - cm;
-        if (per) {
-          sx = wrapc(sx, sd.nx);
-          sy = (DIM == 3) ? wrapc(sy, sd.nyp) : 0;
-          sm = wrapc(sm, sd.nm);
-          unk[i] = false;
+        const int ps = (cm == 1) ? sp : ((cm == -1) ? sn : sc);
+        const int node = nodeo - cy * HX - cx;
+        const T gy_ = ST::ld(&gy_r[i]);
+        const T gx_ = ST::ld(&gx_r[i]);
+        const T Acoef = parS[ps][0][node];
+        const T Bcoef = parS[ps][1][node];
+        const T ia2 = parS[ps][NP - 1][node];
+        const T src = T(LP::W[i]) * (Bcoef + eC(i, ps, node));
+        if constexpr (OFF) {
+          const T phx = phiS[rs(m - cm)][pco - cy * PX - cx];
+          const T hs = Acoef * gx_ + src;
+          d[i] = gy_ + ia2 * (T(LP::W[i]) * (phx - phy) + hs - gy_);
         } else {
-          unk[i] = !(in_range(sx, sd.nx) && (DIM == 2 || in_range(sy, sd.nyp)) && in_range(sm, sd.nm));
+          const T gs = Acoef * gx_ + src;
+          d[i] = gy_ + ia2 * (gs - gy_);
         }
-        const unsigned isrc = unk[i] ? iy : lin(sd, sx, sy, sm);
-        gy_r[i] = ldb(gfield(i), iyb);
-        gx_r[i] = ldb(gfield(i), isrc * (unsigned)sizeof(S));
       }
-    }
-    const T phy = phiS[rs(m)][pco];
-    T d[QP];
-#pragma unroll
-    for (int i = 0; i < QP; ++i) {
-      const int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
-      const int ps = (cm == 1) ? sp : ((cm == -1) ? sn : sc);
-      const int node = nodeo - cy * HX - cx;
-      const T gy_ = ST::ld(&gy_r[i]);
-      const T gx_ = ST::ld(&gx_r[i]);
-      const T Acoef = parS[ps][0][node];
-      const T Bcoef = parS[ps][1][node];
-      const T ia2 = parS[ps][NP - 1][node];
-      const T src = T(LP::W[i]) * (Bcoef + eC(i, ps, node));
-      if constexpr (OFF) {
-        const T phx = phiS[rs(m - cm)][pco - cy * PX - cx];
-        const T hs = Acoef * gx_ + src;
-        d[i] = gy_ + ia2 * (T(LP::W[i]) * (phx - phy) + hs - gy_);
-      } else {
-        const T gs = Acoef * gx_ + src;
-        d[i] = gy_ + ia2 * (gs - gy_);
+      if (walls) {
+        // bounce-back: an unknown incoming population takes the opposite one; if
+        // that is unknown too, the local post-collision opposite population
+        T dn[QP];
+  #pragma unroll
+        for (int i = 0; i < QP; ++i) {
+          const int j = LP::OPP[i];
+          const T loc = parS[sc][0][nodeo] * ST::ld(&gy_r[j]) + T(LP::W[j]) * (parS[sc][1][nodeo] + eC(j, sc, nodeo));
+          dn[i] = unk[i] ? (unk[j] ? loc : d[j]) : d[i];
+        }
+  #pragma unroll
+        for (int i = 0; i < QP; ++i) d[i] = dn[i];
       }
-    }
-    if (walls) {
-      // bounce-back: an unknown incoming population takes the opposite one; if
-      // that is unknown too, the local post-collision opposite population
-      T dn[QP];
-#pragma unroll
+      T sum = T(0);
+  #pragma unroll
+      for (int i = 0; i < QP; ++i) sum += d[i];
+      const T phn = OFF ? phy + sum : sum;
+  #pragma unroll
       for (int i = 0; i < QP; ++i) {
-        const int j = LP::OPP[i];
-        const T loc = parS[sc][0][nodeo] * ST::ld(&gy_r[j]) + T(LP::W[j]) * (parS[sc][1][nodeo] + eC(j, sc, nodeo));
-        dn[i] = unk[i] ? (unk[j] ? loc : d[j]) : d[i];
+        const T v = OFF ? d[i] - T(LP::W[i]) * sum : d[i];
+        ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(gofield(i)) + iyb), v);
       }
-#pragma unroll
-      for (int i = 0; i < QP; ++i) d[i] = dn[i];
-    }
-    T sum = T(0);
-#pragma unroll
-    for (int i = 0; i < QP; ++i) sum += d[i];
-    const T phn = OFF ? phy + sum : sum;
-#pragma unroll
-    for (int i = 0; i < QP; ++i) {
-      const T v = OFF ? d[i] - T(LP::W[i]) * sum : d[i];
-      ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(gofield(i)) + iyb), v);
-    }
-    stb(Phout, iy * (unsigned)sizeof(PT), (PT)phn);
+      stb(Phout, iy * (unsigned)sizeof(PT), (PT)phn);
 
-    // heat equation at y: BGK toward w_i u^n with source (phi^{n+1} - phi^n)/2
-    const T half_dphi = T(0.5) * (phn - phy);
-    const T om_u = T(sd.omega_u);
-    if constexpr (OFF) {
-      const T Sm = u_cur - us_cur;  // sum of the decoded offsets
-      const T keep = T(1) - om_u;
-#pragma unroll
-      for (int i = 0; i < QU; ++i)
-        ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(i)) + iyb), keep * (fd_cur[i] - T(LU::W[i]) * Sm));
-      stb(sd.us_out, iy * 4u, float(u_cur + half_dphi));
-    } else {
-#pragma unroll
-      for (int i = 0; i < QU; ++i) {
-        const T fi = fd_cur[i];
-        ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(i)) + iyb),
-               fi - om_u * (fi - T(LU::W[i]) * u_cur) + T(LU::W[i]) * half_dphi);
+      // heat equation at y: BGK toward w_i u^n with source (phi^{n+1} - phi^n)/2
+      const T half_dphi = T(0.5) * (phn - phy);
+      const T om_u = T(sd.omega_u);
+      if constexpr (OFF) {
+        const T Sm = u_cur - us_cur;  // sum of the decoded offsets
+        const T keep = T(1) - om_u;
+  #pragma unroll
+        for (int i = 0; i < QU; ++i)
+          ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(i)) + iyb), keep * (fd_cur[i] - T(LU::W[i]) * Sm));
+        stb(sd.us_out, iy * 4u, float(u_cur + half_dphi));
+      } else {
+  #pragma unroll
+        for (int i = 0; i < QU; ++i) {
+          const T fi = fd_cur[i];
+          ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(i)) + iyb),
+                 fi - om_u * (fi - T(LU::W[i]) * u_cur) + T(LU::W[i]) * half_dphi);
+        }
       }
+      if constexpr (IDS) stb(sd.id_out, iy * 2u, id_cur);
+    };
+
+    // planes whose pulls can meet a wall (only then is bounce-back applied)
+    const bool xy_walls = !per && !xy_in1;
+    auto walls_at = [&](int m) { return !per && (xy_walls || m == 0 || m == sd.nm - 1); };
+
+    // ---- warm-up ----------------------------------------------------------------
+    // ring planes m0-2 .. m0+1; coefficients of planes m0-1 and m0 (gathers
+    // loaded on the spot); then ring plane m0+2 and the gathers of plane m0+1
+    for (int pm = m0 - 2; pm <= m0 + 1; ++pm) {
+      ring_fetch(pm);
+      ring_commit(pm);
     }
-    if constexpr (IDS) stb(sd.id_out, iy * 2u, id_cur);
-  };
-
-  // planes whose pulls can meet a wall (only then is bounce-back applied)
-  const bool xy_walls = !per && !xy_in1;
-  auto walls_at = [&](int m) { return !per && (xy_walls || m == 0 || m == sd.nm - 1); };
-
-  // ---- warm-up ----------------------------------------------------------------
-  // ring planes m0-2 .. m0+1; coefficients of planes m0-1 and m0 (gathers
-  // loaded on the spot); then ring plane m0+2 and the gathers of plane m0+1
-  for (int pm = m0 - 2; pm <= m0 + 1; ++pm) {
-    ring_fetch(pm);
-    ring_commit(pm);
-  }
-  __syncthreads();
-  for (int pm = m0 - 1; pm <= m0; ++pm) {
-    const int ps = (pm == m0) ? sc : sp;
-    gather_fetch(hx_o, hy_o, pm, kv_o_c);
-    if (has_h) gather_fetch(hx_h, hy_h, pm, kv_h_c);
-    param_node(hx_o, hy_o, pm, ps, kv_o_c, true);
-    if (has_h) param_node(hx_h, hy_h, pm, ps, kv_h_c, false);
-  }
-  __syncthreads();
-  ring_fetch(m0 + 2);
-  ring_commit(m0 + 2);
-  gather_fetch(hx_o, hy_o, m0 + 1, kv_o_c);
-  if (has_h) gather_fetch(hx_h, hy_h, m0 + 1, kv_h_c);
-#pragma unroll
-  for (int i = 0; i < QU; ++i) fd_cur[i] = fd_nxt[i];
-  u_cur = u_nxt;
-  us_cur = us_nxt;
-  id_cur = id_nxt;
-  __syncthreads();
-
-  for (int m = m0; m < m1; ++m) {
-    // loads for the next iterations: ring plane m+3, gathers of plane m+2
-    const bool more_ring = m + 3 <= m1 + 1;
-    if (more_ring) ring_fetch(m + 3);
-    if (m + 2 <= m1) {
-      gather_fetch(hx_o, hy_o, m + 2, kv_o_n);
-      if (has_h) gather_fetch(hx_h, hy_h, m + 2, kv_h_n);
-    }
-    // A: coefficients of plane m+1 (LDS and prefetched registers only)
-    param_node(hx_o, hy_o, m + 1, sn, kv_o_c, true);
-    if (has_h) param_node(hx_h, hy_h, m + 1, sn, kv_h_c, false);
     __syncthreads();
-    // B: plane m
-    if (own) output(m, walls_at(m));
-    if (more_ring) ring_commit(m + 3);
-    __syncthreads();
-    // rotate the coefficient ring, the own-column state and the prefetches
-    const int t = sp;
-    sp = sc;
-    sc = sn;
-    sn = t;
-#pragma unroll
-    for (int i = 0; i < QU; ++i) {
-      fd_cur[i] = fd_nxt[i];
-      kv_o_c[i] = kv_o_n[i];
-      kv_h_c[i] = kv_h_n[i];
+    for (int pm = m0 - 1; pm <= m0; ++pm) {
+      const int ps = (pm == m0) ? sc : sp;
+      gather_fetch(hx_o, hy_o, pm, kv_o_c);
+      if (has_h) gather_fetch(hx_h, hy_h, pm, kv_h_c);
+      param_node(hx_o, hy_o, pm, ps, kv_o_c, true);
+      if (has_h) param_node(hx_h, hy_h, pm, ps, kv_h_c, false);
     }
+    __syncthreads();
+    ring_fetch(m0 + 2);
+    ring_commit(m0 + 2);
+    gather_fetch(hx_o, hy_o, m0 + 1, kv_o_c);
+    if (has_h) gather_fetch(hx_h, hy_h, m0 + 1, kv_h_c);
+  #pragma unroll
+    for (int i = 0; i < QU; ++i) fd_cur[i] = fd_nxt[i];
     u_cur = u_nxt;
     us_cur = us_nxt;
     id_cur = id_nxt;
+    __syncthreads();
+
+    for (int m = m0; m < m1; ++m) {
+      // loads for the next iterations: ring plane m+3, gathers of plane m+2
+      const bool more_ring = m + 3 <= m1 + 1;
+      if (more_ring) ring_fetch(m + 3);
+      if (m + 2 <= m1) {
+        gather_fetch(hx_o, hy_o, m + 2, kv_o_n);
+        if (has_h) gather_fetch(hx_h, hy_h, m + 2, kv_h_n);
+      }
+      // A: coefficients of plane m+1 (LDS and prefetched registers only)
+      param_node(hx_o, hy_o, m + 1, sn, kv_o_c, true);
+      if (has_h) param_node(hx_h, hy_h, m + 1, sn, kv_h_c, false);
+      __syncthreads();
+      // B: plane m
+      if (own) output(m, walls_at(m));
+      if (more_ring) ring_commit(m + 3);
+      __syncthreads();
+      // rotate the coefficient ring, the own-column state and the prefetches
+      const int t = sp;
+      sp = sc;
+      sc = sn;
+      sn = t;
+  #pragma unroll
+      for (int i = 0; i < QU; ++i) {
+        fd_cur[i] = fd_nxt[i];
+        kv_o_c[i] = kv_o_n[i];
+        kv_h_c[i] = kv_h_n[i];
+      }
+      u_cur = u_nxt;
+      us_cur = us_nxt;
+      id_cur = id_nxt;
+    }
+    if constexpr (!BATCH) break;
   }
 }
 
@@ -571,7 +594,7 @@ template <int DIM, int TY, class ST, bool IDS>
 static hipError_t launch_step_t(const SimDev &sd, const TileDev &tc, hipStream_t st) {
   const int nblocks = tc.tiles_x * tc.tiles_y * tc.nchunks;
   dim3 block(64, DIM == 3 ? TY : 1);
-  hipLaunchKernelGGL((step_kernel<DIM, TY, ST, IDS>), dim3(nblocks), block, 0, st, sd, tc);
+  hipLaunchKernelGGL((step_kernel<DIM, TY, ST, IDS, false>), dim3(nblocks), block, 0, st, sd, tc, nullptr, nullptr, 0);
   return hipGetLastError();
 }
 
@@ -610,6 +633,43 @@ hipError_t launch_step(int dim, int storage, const SimDev &sd, const TileDev &tc
     }
   }
   return hipErrorInvalidValue;
+}
+
+template <class ST, bool IDS>
+static hipError_t launch_batch_t(const SimDev *sims, const BatchItem *items, int n_items, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((step_kernel<2, 1, ST, IDS, true>), dim3(grid), dim3(64), 0, st, SimDev{}, TileDev{}, sims, items,
+                     n_items);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch(int storage, bool ids, const SimDev *sims, const BatchItem *items, int n_items, int grid,
+                        hipStream_t st) {
+  if (n_items < 1 || grid < 1) return hipErrorInvalidValue;
+  switch (storage) {
+    case 0: return ids ? launch_batch_t<StF64, true>(sims, items, n_items, grid, st)
+                       : launch_batch_t<StF64, false>(sims, items, n_items, grid, st);
+    case 1: return ids ? launch_batch_t<StF32, true>(sims, items, n_items, grid, st)
+                       : launch_batch_t<StF32, false>(sims, items, n_items, grid, st);
+    case 2: return ids ? launch_batch_t<StF16, true>(sims, items, n_items, grid, st)
+                       : launch_batch_t<StF16, false>(sims, items, n_items, grid, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <class ST, bool IDS> static int batch_occupancy_t() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<2, 1, ST, IDS, true>, 64, 0) != hipSuccess)
+    return 0;
+  return nb;
+}
+
+int batch_blocks_per_cu(int storage, bool ids) {
+  switch (storage) {
+    case 0: return ids ? batch_occupancy_t<StF64, true>() : batch_occupancy_t<StF64, false>();
+    case 1: return ids ? batch_occupancy_t<StF32, true>() : batch_occupancy_t<StF32, false>();
+    case 2: return ids ? batch_occupancy_t<StF16, true>() : batch_occupancy_t<StF16, false>();
+  }
+  return 0;
 }
 
 }  // namespace lbpf
