@@ -133,6 +133,41 @@ def run_batched(steps: int, warmup: int):
                          "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_node_step": b_alg}}
 
 
+def run_accuracy(workload: str, n: int, steps: int, every: int, variant: str):
+    """Error of the FP32- and FP16-offset forms against the FP64 form (itself
+    checked against the FP64 oracle) over a run: max |d phi|, max |d u|,
+    |d solid fraction| and |d tip| every `every` steps, one JSON line each."""
+    import torch
+
+    import paper_1606_09432_amd as lb
+    from paper_1606_09432_amd import workloads as W
+
+    make = (lambda st: W.c2(st, n=n)) if workload == "c2" else (lambda st: W.c3(st, variant, n=n))
+    sims = {st: lb.Simulation(make(st)) for st in ("fp64", "fp32", "fp16")}
+    done = 0
+    while True:
+        ref_phi, ref_u, _ = sims["fp64"].fields()
+        ref_d = sims["fp64"].diagnostics()[0]
+        row = {"workload": workload, "n": n, "step": done, "tip_fp64": ref_d["tip_position"],
+               "solid_fraction_fp64": ref_d["solid_fraction"]}
+        for st in ("fp32", "fp16"):
+            phi, u, _ = sims[st].fields()
+            d = sims[st].diagnostics()[0]
+            row[st] = {"max_dphi": float((phi - ref_phi).abs().max()), "max_du": float((u - ref_u).abs().max()),
+                       "d_solid_fraction": abs(d["solid_fraction"] - ref_d["solid_fraction"]),
+                       "d_tip": abs(d["tip_position"] - ref_d["tip_position"])}
+            del phi, u
+        del ref_phi, ref_u
+        print(json.dumps(row), flush=True)
+        if done >= steps:
+            break
+        k = min(every, steps - done)
+        for sim in sims.values():
+            sim.step(k)
+        torch.cuda.synchronize()
+        done += k
+
+
 def cpu_baseline(cfg_full, sample_n: int, sample_steps: int):
     """The CPU FP64 oracle on a bounded sample: the same parameters on a
     sample_n^3 box around the seed, sample_steps steps."""
@@ -253,6 +288,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--only", choices=["fp16", "fp64", "fp32"], default=None)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 2D ensemble")
+    ap.add_argument("--accuracy", choices=["c2", "c3"], default=None,
+                    help="only report the FP32/FP16-offset error against FP64 over a run")
+    ap.add_argument("--acc-steps", type=int, default=2000)
+    ap.add_argument("--acc-every", type=int, default=500)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (for HBM counter calibration)")
     ap.add_argument("--summarize-trace", metavar="DIR", help="write a markdown summary of a --kernel-trace run")
@@ -271,6 +310,10 @@ def main():
         res, md = summarize_traffic(*args.summarize_traffic, args.copy_mib * (1 << 20), args.command)
         json.dump(res, open(TRAFFIC_FILE, "w"), indent=1)
         open(args.out, "w").write(md) if args.out else print(md)
+        return
+    if args.accuracy:
+        run_accuracy(args.accuracy, args.n if args.accuracy == "c3" else min(args.n, 256), args.acc_steps,
+                     args.acc_every, args.variant)
         return
     if args.calibrate_copy:
         # a plain elementwise copy kernel (read n bytes, write n bytes)
