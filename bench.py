@@ -17,6 +17,7 @@ import argparse
 import glob
 import hashlib
 import json
+import math
 import os
 import sqlite3
 import sys
@@ -168,6 +169,76 @@ def run_accuracy(workload: str, n: int, steps: int, every: int, variant: str):
         done += k
 
 
+def profile_l2_error(phi, centre, n_a=(1.0, 0.0), n_b=(0.5, -math.sqrt(3.0) / 2.0), length=None) -> float:
+    """Relative l2 difference of two phi profiles sampled from `centre` along
+    the unit directions n_a and n_b at unit spacing (Eq. Error_L2), phi_a the
+    reference.  Off-lattice points use cubic convolution (Keys, a = -1/2),
+    whose error on a resolved tanh front is far below the bilinear one.
+    phi is [y][x]."""
+    import numpy as np
+
+    ny, nx = phi.shape
+    cx, cy = centre
+    if length is None:
+        length = int(min(nx - 3 - cx, cx - 2, ny - 3 - cy, cy - 2))
+
+    def w(t):  # Keys cubic convolution weights for offsets -1, 0, 1, 2
+        t2, t3 = t * t, t * t * t
+        return [(-t3 + 2 * t2 - t) / 2, (3 * t3 - 5 * t2 + 2) / 2, (-3 * t3 + 4 * t2 + t) / 2, (t3 - t2) / 2]
+
+    def sample(d):
+        j = np.arange(length + 1, dtype=np.float64)
+        x = cx + j * d[0]
+        y = cy + j * d[1]
+        x0 = np.floor(x).astype(int)
+        y0 = np.floor(y).astype(int)
+        wx, wy = w(x - x0), w(y - y0)
+        out = np.zeros_like(x)
+        for a in range(4):
+            for b in range(4):
+                out += wy[a] * wx[b] * phi[y0 + a - 1, x0 + b - 1]
+        return out
+
+    pa, pb = sample(n_a), sample(n_b)
+    return float(np.sqrt(np.sum((pa - pb) ** 2) / np.sum(pa ** 2)))
+
+
+def run_isotropy(steps: int, storage: str):
+    """The isotropy comparison of Sec. 4.2 (six-fold a_s, 800^2): the DD and CD
+    runs advance together as one batched ensemble; prints Err_l2 of each and
+    the throughput."""
+    import numpy as np
+    import torch
+
+    import paper_1606_09432_amd as lb
+    from paper_1606_09432_amd import workloads as W
+
+    cfgs = [W.e2("dd", storage=storage), W.e2("cd", storage=storage)]
+    sim = lb.Simulation(cfgs)
+    done, every = 0, max(1, steps // 10)
+    t_ms = 0.0
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    while done < steps:
+        k = min(every, steps - done)
+        e0.record()
+        sim.step(k)
+        e1.record()
+        torch.cuda.synchronize()
+        t_ms += e0.elapsed_time(e1)
+        done += k
+        print(f"[e2] step {done}", file=sys.stderr, flush=True)
+    out = {"workload": "isotropy comparison, six-fold a_s, 800^2, DD and CD in one batch", "steps": steps,
+           "storage": storage, "MLUPS": 2 * cfgs[0].nodes * steps / (t_ms * 1e-3) / 1e6}
+    for k, name in enumerate(("dd", "cd")):
+        phi = sim.fields(k)[0].cpu().numpy()
+        c = cfgs[k].seeds[0]
+        out[f"err_l2_{name}"] = profile_l2_error(phi, (c.x, c.y))
+        out[f"tip_{name}"] = sim.diagnostics()[k]["tip_position"]
+    out["cd_over_dd"] = out["err_l2_cd"] / out["err_l2_dd"]
+    return out
+
+
 def cpu_baseline(cfg_full, sample_n: int, sample_steps: int):
     """The CPU FP64 oracle on a bounded sample: the same parameters on a
     sample_n^3 box around the seed, sample_steps steps."""
@@ -290,6 +361,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 2D ensemble")
     ap.add_argument("--accuracy", choices=["c2", "c3"], default=None,
                     help="only report the FP32/FP16-offset error against FP64 over a run")
+    ap.add_argument("--isotropy", type=int, default=0, metavar="STEPS",
+                    help="only run the six-fold DD/CD isotropy comparison for STEPS steps")
     ap.add_argument("--acc-steps", type=int, default=2000)
     ap.add_argument("--acc-every", type=int, default=500)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -310,6 +383,9 @@ def main():
         res, md = summarize_traffic(*args.summarize_traffic, args.copy_mib * (1 << 20), args.command)
         json.dump(res, open(TRAFFIC_FILE, "w"), indent=1)
         open(args.out, "w").write(md) if args.out else print(md)
+        return
+    if args.isotropy:
+        print(json.dumps(run_isotropy(args.isotropy, args.only or "fp64")), flush=True)
         return
     if args.accuracy:
         run_accuracy(args.accuracy, args.n if args.accuracy == "c3" else min(args.n, 256), args.acc_steps,

@@ -211,6 +211,24 @@ def c4(count: int = 256, rng_seed: int = 160604, storage: str = "fp32",
 C4_STEPS = 5000
 
 
+def e2(gradient: str = "dd", n: int = 800, storage: str = "fp64") -> SimConfig:
+    """The isotropy comparison of Sec. 4.2: six-fold a_s (Eq. As_Theta, q = 6,
+    phi0 = 0, eps = 0.05), 800^2, seed R = 10 lu at (400, 400), dx = 0.01,
+    dt = 1.5e-5, tau0 = 1.5625e-4, W0 = 0.0125, kappa = 1, Delta = 0.3,
+    lambda = 10 (lattice units: W0/dx = 1.25, Dphi = 0.15, dt/tau0 = 0.096,
+    Du = 0.15); gradients by directional derivatives or central differences.
+    The walls are not stated; zero flux is used."""
+    c = n // 2
+    return SimConfig(
+        lattice="D2Q9_D2Q5", nx=n, ny=n, nz=1, boundary="zero_flux", gradient=gradient,
+        storage=storage, W0=0.0125, tau0=1.5625e-4, lam=10.0, kappa=1.0, delta=0.3,
+        dx=0.01, dt=1.5e-5, aniso=[Aniso("sectoral", eps=0.05, q=6, phi0=0.0)],
+        seeds=[Seed(c, c, 0.0, 10.0, 1)], tip_dir=(1, 0, 0))
+
+
+E2_STEPS = 100000
+
+
 def small_3d(storage: str = "fp64", n: int = 48, aniso: Aniso | None = None,
              boundary: str = "zero_flux", radius: float = 6.0, delta: float = 0.55,
              nx: int | None = None, ny: int | None = None, nz: int | None = None) -> SimConfig:

@@ -358,6 +358,26 @@ def test_c4_full_ensemble(gpu, oracle_mod):
 
 
 # ---------------------------------------------------------------------------
+# The isotropy comparison of Sec. 4.2 (six-fold a_s, 800^2).
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("grad", ["dd", "cd"])
+def test_e2_parity_window(gpu, oracle_mod, grad):
+    _compare(gpu, oracle_mod, W.e2(grad), 200)
+
+
+def test_e2_isotropy_dd_vs_cd(gpu):
+    """Full length (1e5 steps): the profiles along n_a = (1, 0) and
+    n_b = (1/2, -sqrt(3)/2) differ far less with directional derivatives than
+    with central differences (the paper reports 3.04e-3 and 1.71e-1)."""
+    import bench
+    _say(f"isotropy comparison, DD and CD batched, {W.E2_STEPS} steps")
+    r = bench.run_isotropy(W.E2_STEPS, "fp64")
+    _say(f"  {r}")
+    assert r["err_l2_dd"] < 1e-2
+    assert r["cd_over_dd"] >= 10
+
+
+# ---------------------------------------------------------------------------
 # Properties that hold at any size.
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("storage,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
