@@ -31,6 +31,7 @@ HBM_PEAK_GBS = 8000.0
 # Algorithmic bytes per node-step: every distribution read once and written
 # once; offset forms also read and write the FP32 phi and u* fields.
 B_ALG = {("D3Q19_D3Q7", "fp64"): 416, ("D3Q19_D3Q7", "fp32"): 224, ("D3Q19_D3Q7", "fp16"): 120,
+         ("D3Q15_D3Q7", "fp64"): 352, ("D3Q15_D3Q7", "fp32"): 192, ("D3Q15_D3Q7", "fp16"): 104,
          ("D2Q9_D2Q5", "fp64"): 224, ("D2Q9_D2Q5", "fp32"): 128, ("D2Q9_D2Q5", "fp16"): 72}
 KERNEL_SOURCES = ["paper_1606_09432_amd/csrc/lbpf_step.hip", "paper_1606_09432_amd/csrc/lbpf_common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
@@ -43,14 +44,18 @@ def kernel_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage: str):
+def traffic_key(lattice: str, storage: str) -> str:
+    return storage if lattice == "D3Q19_D3Q7" else f"{lattice.split('_')[0].lower()}_{storage}"
+
+
+def measured_traffic(lattice: str, storage: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    ent = d.get("kernels", {}).get(storage)
+    ent = d.get("kernels", {}).get(traffic_key(lattice, storage))
     if not ent or ent.get("kernel_sha") != kernel_sha():
         return None
     return ent.get("bytes_per_launch")
@@ -83,7 +88,7 @@ def run_gpu(cfg, steps: int, warmup: int, autotune: bool):
     mlups = nodes * steps / (ms * 1e-3) / 1e6
     b_alg = B_ALG[(cfg.lattice, cfg.storage)]
     achieved = b_alg * nodes / (ms / steps * 1e-3) / 1e9
-    traffic = measured_traffic(cfg.storage)
+    traffic = measured_traffic(cfg.lattice, cfg.storage)
     print(f"[bench] {cfg.storage}: {ms / steps:.3f} ms/step  {mlups:.1f} MLUPS  {achieved:.0f} GB/s "
           f"tile={tile} tip={diag['tip_position']:.3f}", file=sys.stderr, flush=True)
     return {
@@ -296,6 +301,9 @@ def summarize_trace(d, command, bench_json=None):
             if st in b:
                 out.append(f"- {st}: {b[st]['ms_per_step']:.4f} ms, {b[st]['value']:.1f} {b[st]['unit']}, "
                            f"{b[st]['roofline']['achieved']:.0f} GB/s algorithmic")
+        for st, r in b.get("d3q15", {}).items():
+            out.append(f"- D3Q15 {st}: {r['ms_per_step']:.4f} ms, {r['value']:.1f} {r['unit']}, "
+                       f"{r['roofline']['achieved']:.0f} GB/s algorithmic")
     return "\n".join(out) + "\n"
 
 
@@ -329,12 +337,13 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, 
           "| kernel | FETCH_SIZE | WRITE_SIZE | read bytes | written bytes | bytes/launch | bytes/node |",
           "|---|---|---|---|---|---|---|"]
     for k in sorted(set(fe) | set(wr)):
-        if not k.startswith("step_kernel<3,"):  # the 3D workload's kernel
-            continue
+        # the 3D workload's kernels: lattice pair 1 (D3Q19) or 2 (D3Q15)
+        lat = {"step_kernel<1,": "D3Q19_D3Q7", "step_kernel<2,": "D3Q15_D3Q7"}.get(k[:14])
         st = next((v for kk, v in STORAGE_OF_KERNEL.items() if kk in k), None)
         f, w = fe.get(k, {}).get("FETCH_SIZE"), wr.get(k, {}).get("WRITE_SIZE")
-        if st is None or f is None or w is None:
+        if lat is None or st is None or f is None or w is None:
             continue
+        st = traffic_key(lat, st)
         rb, wb = f * ff, w * fw
         nodes = 512 ** 3
         res["kernels"][st] = {"kernel": k, "kernel_sha": sha, "fetch_counter": f, "write_counter": w,
@@ -359,6 +368,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--only", choices=["fp16", "fp64", "fp32"], default=None)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 2D ensemble")
+    ap.add_argument("--no-d3q15", action="store_true", help="skip the D3Q15 runs")
     ap.add_argument("--accuracy", choices=["c2", "c3"], default=None,
                     help="only report the FP32/FP16-offset error against FP64 over a run")
     ap.add_argument("--isotropy", type=int, default=0, metavar="STEPS",
@@ -433,6 +443,14 @@ def main():
         out["fp16_over_fp64"] = results["fp16"]["value"] / results["fp64"]["value"]
     if not args.no_batched and not args.only:
         out["batched"] = run_batched(args.steps, args.warmup)
+    if not args.no_d3q15 and not args.only:
+        # the paper's own 3D phase-field lattice on the same workload
+        out["d3q15"] = {}
+        for st in ("fp16", "fp64"):
+            rr = run_gpu(W.c3(st, args.variant, n=args.n, lattice="D3Q15_D3Q7"), args.steps, args.warmup,
+                         args.autotune)
+            out["d3q15"][st] = {"value": rr["value"], "unit": "MLUPS", "ms_per_step": rr["ms_per_step"],
+                                "roofline": rr["roofline"], "tile_y_chunk": rr["tile"]}
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W.c3("fp64", args.variant, n=args.n), args.cpu_sample, args.cpu_steps)

@@ -58,9 +58,12 @@ extern "C" {
 #define LBPF_ERR_NONFINITE (-5)   /* diagnostics found a non-finite phi or u */
 #define LBPF_ERR_UNSUPPORTED (-6) /* valid request this build does not implement */
 
-/* Lattice pairs (Sec. 3.3). */
+/* Lattice pairs (Sec. 3.3): phi lattice + u lattice.  D3Q15 is the paper's own
+ * 3D phi lattice (Table Values-Lattices); D3Q19 takes the standard weights
+ * 1/3, 1/18, 1/36. */
 #define LBPF_D2Q9_D2Q5 0
 #define LBPF_D3Q19_D3Q7 1
+#define LBPF_D3Q15_D3Q7 2
 /* Boundaries: periodic box, or zero flux on every wall (Sec. 2, Eq. Bounce-Back). */
 #define LBPF_PERIODIC 0
 #define LBPF_ZERO_FLUX 1
@@ -94,7 +97,7 @@ typedef struct {
 } lbpf_seed;
 
 typedef struct {
-  int32_t lattice;   /* LBPF_D2Q9_D2Q5 or LBPF_D3Q19_D3Q7 */
+  int32_t lattice;   /* LBPF_D2Q9_D2Q5, LBPF_D3Q19_D3Q7 or LBPF_D3Q15_D3Q7 */
   int32_t nx, ny, nz;/* nz = 1 in 2D; every used extent >= 3 */
   int32_t boundary;  /* LBPF_PERIODIC or LBPF_ZERO_FLUX */
   int32_t gradient;  /* LBPF_GRAD_DD or LBPF_GRAD_CD */

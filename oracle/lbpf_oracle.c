@@ -83,7 +83,7 @@ static void lat_set_dir(lat_t *L, int i, int x, int y, int z, double w) {
   L->w[i] = w;
 }
 
-/* which: 0 D2Q5, 1 D2Q9, 2 D3Q7, 3 D3Q19 */
+/* which: 0 D2Q5, 1 D2Q9, 2 D3Q7, 3 D3Q19, 4 D3Q15 */
 static int lat_make(int which, lat_t *L) {
   memset(L, 0, sizeof(*L));
   switch (which) {
@@ -147,6 +147,26 @@ static int lat_make(int which, lat_t *L) {
     L->e2 = 1.0 / 3.0;
     L->inv_e2 = 3.0;
     break;
+  case 4: /* D3Q15 (Table Values-Lattices): 2/9, 1/9, 1/72; the paper's order */
+    L->q = 15;
+    lat_set_dir(L, 0, 0, 0, 0, 2.0 / 9.0);
+    lat_set_dir(L, 1, 1, 0, 0, 1.0 / 9.0);
+    lat_set_dir(L, 2, 0, 1, 0, 1.0 / 9.0);
+    lat_set_dir(L, 3, -1, 0, 0, 1.0 / 9.0);
+    lat_set_dir(L, 4, 0, -1, 0, 1.0 / 9.0);
+    lat_set_dir(L, 5, 0, 0, 1, 1.0 / 9.0);
+    lat_set_dir(L, 6, 0, 0, -1, 1.0 / 9.0);
+    lat_set_dir(L, 7, 1, 1, 1, 1.0 / 72.0);
+    lat_set_dir(L, 8, -1, 1, 1, 1.0 / 72.0);
+    lat_set_dir(L, 9, -1, -1, 1, 1.0 / 72.0);
+    lat_set_dir(L, 10, 1, -1, 1, 1.0 / 72.0);
+    lat_set_dir(L, 11, 1, 1, -1, 1.0 / 72.0);
+    lat_set_dir(L, 12, -1, 1, -1, 1.0 / 72.0);
+    lat_set_dir(L, 13, -1, -1, -1, 1.0 / 72.0);
+    lat_set_dir(L, 14, 1, -1, -1, 1.0 / 72.0);
+    L->e2 = 1.0 / 3.0;
+    L->inv_e2 = 3.0;
+    break;
   default:
     return -1;
   }
@@ -164,6 +184,9 @@ static double lat_sum(const lat_t *L, const double *v) {
     return v[0] + (((v[1] + v[3]) + (v[2] + v[4])) + ((v[5] + v[7]) + (v[6] + v[8])));
   case 7:
     return v[0] + (((v[1] + v[3]) + (v[2] + v[4])) + (v[5] + v[6]));
+  case 15:
+    return v[0] + ((((v[1] + v[3]) + (v[2] + v[4])) + (v[5] + v[6])) +
+                   (((v[7] + v[9]) + (v[8] + v[10])) + ((v[11] + v[13]) + (v[12] + v[14]))));
   default: /* 19 */
     return v[0] + ((((v[1] + v[3]) + (v[2] + v[4])) + (v[5] + v[6])) +
                    (((v[7] + v[9]) + (v[8] + v[10])) +
@@ -604,6 +627,9 @@ int orc_create(const orc_config *cfg, orc_sim **out) {
   if (cfg->nx < 3 || cfg->ny < 3) return -1;
   if (cfg->dim == 2 && cfg->nz != 1) return -1;
   if (cfg->dim == 3 && cfg->nz < 3) return -1;
+  if (!(cfg->q_phi == 0 || (cfg->dim == 2 && cfg->q_phi == 9) ||
+        (cfg->dim == 3 && (cfg->q_phi == 19 || cfg->q_phi == 15))))
+    return -1;
   if (!(cfg->W0 > 0 && cfg->tau0 > 0 && cfg->dx > 0 && cfg->dt > 0 && cfg->kappa > 0)) return -2;
   if (cfg->n_aniso < 1 || cfg->aniso == NULL) return -1;
   for (int k = 0; k < cfg->n_aniso; ++k) {
@@ -623,7 +649,7 @@ int orc_create(const orc_config *cfg, orc_sim **out) {
   if (cfg->n_seeds > 0) memcpy(S->seeds, cfg->seeds, sizeof(orc_seed) * cfg->n_seeds);
   S->cfg.aniso = S->aniso;
   S->cfg.seeds = S->seeds;
-  lat_make(cfg->dim == 2 ? 1 : 3, &S->lp);
+  lat_make(cfg->dim == 2 ? 1 : (cfg->q_phi == 15 ? 4 : 3), &S->lp);
   lat_make(cfg->dim == 2 ? 0 : 2, &S->lu);
   S->nx = cfg->nx;
   S->ny = cfg->ny;

@@ -46,7 +46,7 @@ typedef struct {
 } orc_seed;
 
 typedef struct {
-  int32_t dim;          /* 2: D2Q9 phi + D2Q5 u;  3: D3Q19 phi + D3Q7 u */
+  int32_t dim;          /* 2: D2Q9 phi + D2Q5 u;  3: D3Q19 (or D3Q15, q_phi) phi + D3Q7 u */
   int32_t nx, ny, nz;   /* nz must be 1 when dim == 2 */
   int32_t periodic;     /* 1 periodic box, 0 zero flux (bounce-back, Eq. Bounce-Back) */
   int32_t grad_cd;      /* 0 directional derivatives (Eq. Grad_DF-Centree), 1 central differences */
@@ -57,6 +57,7 @@ typedef struct {
   int32_t n_seeds;
   const orc_seed *seeds;
   int32_t tip_dir[3];   /* integer lattice direction of the tip ray from seed 0's centre */
+  int32_t q_phi;        /* phi lattice: 0 default (D2Q9 / D3Q19), or 15 for D3Q15 in 3D */
 } orc_config;
 
 typedef struct orc_sim orc_sim;
@@ -93,6 +94,7 @@ void orc_params(orc_sim *s, double *p, double *a, double *flux, double *eta, dou
 void orc_diagnostics(const orc_sim *s, orc_diag *d);
 
 /* Pointwise pieces, for pinning against closed forms. */
+/* which: 0 D2Q5, 1 D2Q9, 2 D3Q7, 3 D3Q19, 4 D3Q15 */
 int orc_lattice(int which, int *q, int *e /* [q][3] */, double *w, int *opp, double *e2);
 void orc_aniso_eval(const orc_aniso *an, const double n[3], double *a, double G[3]);
 void orc_flux(const orc_aniso *an, const double p[3], double *a, double N[3]);

@@ -36,7 +36,7 @@ class OrcConfig(C.Structure):
                 ("dt", C.c_double), ("xi", C.c_double),
                 ("n_aniso", C.c_int32), ("aniso", C.POINTER(OrcAniso)),
                 ("n_seeds", C.c_int32), ("seeds", C.POINTER(OrcSeed)),
-                ("tip_dir", C.c_int32 * 3)]
+                ("tip_dir", C.c_int32 * 3), ("q_phi", C.c_int32)]
 
 
 class OrcDiag(C.Structure):
@@ -108,6 +108,7 @@ class OracleSim:
         self._keep = (an, sd)
         c = OrcConfig()
         c.dim = 2 if cfg.lattice == "D2Q9_D2Q5" else 3
+        c.q_phi = 15 if cfg.lattice == "D3Q15_D3Q7" else 0
         c.nx, c.ny, c.nz = cfg.nx, cfg.ny, cfg.nz
         c.periodic = 1 if cfg.boundary == "periodic" else 0
         c.grad_cd = 1 if cfg.gradient == "cd" else 0
@@ -193,9 +194,9 @@ class OracleSim:
 
 
 def lattice(which: str):
-    """Lattice tables: which in {'D2Q5', 'D2Q9', 'D3Q7', 'D3Q19'}."""
+    """Lattice tables: which in {'D2Q5', 'D2Q9', 'D3Q7', 'D3Q19', 'D3Q15'}."""
     lib = load()
-    idx = {"D2Q5": 0, "D2Q9": 1, "D3Q7": 2, "D3Q19": 3}[which]
+    idx = {"D2Q5": 0, "D2Q9": 1, "D3Q7": 2, "D3Q19": 3, "D3Q15": 4}[which]
     q = C.c_int()
     e = (C.c_int * 57)()
     w = np.zeros(19)

@@ -24,7 +24,7 @@ __all__ = ["Simulation", "SimConfig", "Aniso", "Seed", "workloads", "load_librar
            "LbpfError", "EXPORTED_SYMBOLS"]
 
 # C ABI mirrors (include/lb_pf.h).
-LATTICE = {"D2Q9_D2Q5": 0, "D3Q19_D3Q7": 1}
+LATTICE = {"D2Q9_D2Q5": 0, "D3Q19_D3Q7": 1, "D3Q15_D3Q7": 2}
 BOUNDARY = {"periodic": 0, "zero_flux": 1}
 GRADIENT = {"dd": 0, "cd": 1}
 STORAGE = {"fp64": 0, "fp32": 1, "fp16": 2}
@@ -232,7 +232,7 @@ class Simulation:
         """Post-streaming (g, f) of simulation `sim`, FP64, shaped [q, *shape]."""
         t = self.torch
         cfg = self.cfgs[sim]
-        qp, qu = (9, 5) if cfg.dim == 2 else (19, 7)
+        qp, qu = (9, 5) if cfg.dim == 2 else ((15, 7) if cfg.lattice == "D3Q15_D3Q7" else (19, 7))
         g = t.empty((qp,) + cfg.shape, dtype=t.float64, device=self.device)
         f = t.empty((qu,) + cfg.shape, dtype=t.float64, device=self.device)
         _check(self.lib.lb_pf_export_dists(self.h, sim, C.c_void_p(g.data_ptr()), C.c_void_p(f.data_ptr()),

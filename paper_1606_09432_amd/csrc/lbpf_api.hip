@@ -85,7 +85,8 @@ struct lbpf_handle {
 namespace {
 
 int validate(const lbpf_config &c) {
-  if (c.lattice != LBPF_D2Q9_D2Q5 && c.lattice != LBPF_D3Q19_D3Q7) return fail(LBPF_ERR_ARG, "unknown lattice");
+  if (c.lattice != LBPF_D2Q9_D2Q5 && c.lattice != LBPF_D3Q19_D3Q7 && c.lattice != LBPF_D3Q15_D3Q7)
+    return fail(LBPF_ERR_ARG, "unknown lattice");
   const int dim = c.lattice == LBPF_D2Q9_D2Q5 ? 2 : 3;
   if (c.nx < 3 || c.ny < 3) return fail(LBPF_ERR_ARG, "nx and ny must be >= 3");
   if (dim == 2 && c.nz != 1) return fail(LBPF_ERR_ARG, "nz must be 1 for the 2D lattice pair");
@@ -173,7 +174,7 @@ void plan(const lbpf_config &c, SimHost &s, size_t &cursor) {
   s.cfg = c;
   s.dim = c.lattice == LBPF_D2Q9_D2Q5 ? 2 : 3;
   s.storage = c.storage;
-  s.qp = s.dim == 2 ? 9 : 19;
+  s.qp = s.dim == 2 ? 9 : (c.lattice == LBPF_D3Q15_D3Q7 ? 15 : 19);
   s.qu = s.dim == 2 ? 5 : 7;
   s.nx = c.nx;
   s.nyp = s.dim == 3 ? c.ny : 1;
@@ -398,7 +399,7 @@ int lb_pf_init(const lbpf_config *cfgs, int n_sims, void *dev_workspace, size_t 
       src.n_seeds = s.cfg.n_seeds;
       src.nx = s.cfg.nx;
       src.ny = s.cfg.ny;
-      e = launch_init(s.dim, s.storage, d, d.id_out, src, st);
+      e = launch_init(s.cfg.lattice, s.storage, d, d.id_out, src, st);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
@@ -515,7 +516,7 @@ int lb_pf_step(lbpf_handle *h, int n_steps, void *hip_stream) {
   for (int n = 0; n < n_steps; ++n) {
     for (const SimHost &s : h->sims) {
       const SimDev d = make_dev(h, s, h->parity);
-      HIPCHK(launch_step(s.dim, s.storage, d, s.tile, st));
+      HIPCHK(launch_step(s.cfg.lattice, s.storage, d, s.tile, st));
     }
     h->parity ^= 1;
     h->step++;
@@ -565,7 +566,7 @@ int lb_pf_export_fields(lbpf_handle *h, int sim, double *phi_dev, double *u_dev,
   int rc = check_sim(h, sim);
   if (rc) return rc;
   const SimHost &s = h->sims[sim];
-  HIPCHK(launch_export(s.dim, s.storage, make_dev(h, s, h->parity), phi_dev, u_dev, ids_dev, nullptr, nullptr,
+  HIPCHK(launch_export(s.cfg.lattice, s.storage, make_dev(h, s, h->parity), phi_dev, u_dev, ids_dev, nullptr, nullptr,
                        s.cfg.ny, static_cast<hipStream_t>(hip_stream)));
   return LBPF_OK;
 }
@@ -574,7 +575,7 @@ int lb_pf_export_dists(lbpf_handle *h, int sim, double *g_dev, double *f_dev, vo
   int rc = check_sim(h, sim);
   if (rc) return rc;
   const SimHost &s = h->sims[sim];
-  HIPCHK(launch_export(s.dim, s.storage, make_dev(h, s, h->parity), nullptr, nullptr, nullptr, g_dev, f_dev,
+  HIPCHK(launch_export(s.cfg.lattice, s.storage, make_dev(h, s, h->parity), nullptr, nullptr, nullptr, g_dev, f_dev,
                        s.cfg.ny, static_cast<hipStream_t>(hip_stream)));
   return LBPF_OK;
 }
@@ -592,7 +593,7 @@ int lb_pf_import_fields(lbpf_handle *h, int sim, const double *phi_dev, const do
   src.ids = ids_dev;
   src.nx = s.cfg.nx;
   src.ny = s.cfg.ny;
-  HIPCHK(launch_init(s.dim, s.storage, d, d.id_out, src, static_cast<hipStream_t>(hip_stream)));
+  HIPCHK(launch_init(s.cfg.lattice, s.storage, d, d.id_out, src, static_cast<hipStream_t>(hip_stream)));
   return LBPF_OK;
 }
 

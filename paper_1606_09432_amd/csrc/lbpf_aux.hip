@@ -43,10 +43,11 @@ __device__ double init_u(const SimDev &sd, const InitSrc &src, int x, int yp, in
   return sd.u0;  // Eq. Intial-Cond_u
 }
 
-template <int DIM, class ST>
+template <int K, class ST>
 __global__ __launch_bounds__(256) void init_kernel(SimDev sd, int16_t *ids_out, InitSrc src) {
-  using LP = typename Lat<DIM>::P;
-  using LU = typename Lat<DIM>::U;
+  constexpr int DIM = LatOf<K>::DIM;
+  using LP = typename LatOf<K>::P;
+  using LU = typename LatOf<K>::U;
   using S = typename ST::S;
   const long long total = (long long)sd.nx * sd.nyp * sd.nm;
   S *G = reinterpret_cast<S *>(sd.g_out);
@@ -141,25 +142,30 @@ __global__ __launch_bounds__(256) void init_kernel(SimDev sd, int16_t *ids_out, 
   }
 }
 
-template <int DIM, class ST>
+template <int K, class ST>
 static hipError_t launch_init_t(const SimDev &sd, int16_t *ids_out, const InitSrc &src, hipStream_t st) {
   const long long total = (long long)sd.nx * sd.nyp * sd.nm;
   long long nb = (total + 255) / 256;
   if (nb > 65536) nb = 65536;
-  hipLaunchKernelGGL((init_kernel<DIM, ST>), dim3((unsigned)nb), dim3(256), 0, st, sd, ids_out, src);
+  hipLaunchKernelGGL((init_kernel<K, ST>), dim3((unsigned)nb), dim3(256), 0, st, sd, ids_out, src);
   return hipGetLastError();
 }
 
-hipError_t launch_init(int dim, int storage, const SimDev &sd, int16_t *ids_out, const InitSrc &src,
+template <int K>
+static hipError_t launch_init_k(int storage, const SimDev &sd, int16_t *ids_out, const InitSrc &src, hipStream_t st) {
+  if (storage == 0) return launch_init_t<K, StF64>(sd, ids_out, src, st);
+  if (storage == 1) return launch_init_t<K, StF32>(sd, ids_out, src, st);
+  return launch_init_t<K, StF16>(sd, ids_out, src, st);
+}
+
+hipError_t launch_init(int lattice, int storage, const SimDev &sd, int16_t *ids_out, const InitSrc &src,
                        hipStream_t st) {
-  if (dim == 2) {
-    if (storage == 0) return launch_init_t<2, StF64>(sd, ids_out, src, st);
-    if (storage == 1) return launch_init_t<2, StF32>(sd, ids_out, src, st);
-    return launch_init_t<2, StF16>(sd, ids_out, src, st);
+  switch (lattice) {
+    case 0: return launch_init_k<0>(storage, sd, ids_out, src, st);
+    case 1: return launch_init_k<1>(storage, sd, ids_out, src, st);
+    case 2: return launch_init_k<2>(storage, sd, ids_out, src, st);
   }
-  if (storage == 0) return launch_init_t<3, StF64>(sd, ids_out, src, st);
-  if (storage == 1) return launch_init_t<3, StF32>(sd, ids_out, src, st);
-  return launch_init_t<3, StF16>(sd, ids_out, src, st);
+  return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------
@@ -277,11 +283,12 @@ hipError_t launch_diag(int dim, int storage, const SimDev &sd, double *partials,
 // ---------------------------------------------------------------------------
 // Export of phi, u, index and decoded post-streaming distributions (FP64).
 // ---------------------------------------------------------------------------
-template <int DIM, class ST>
+template <int K, class ST>
 __global__ __launch_bounds__(256) void export_kernel(SimDev sd, double *phi, double *u, int16_t *ids,
                                                      double *g, double *f) {
-  using LP = typename Lat<DIM>::P;
-  using LU = typename Lat<DIM>::U;
+  constexpr int DIM = LatOf<K>::DIM;
+  using LP = typename LatOf<K>::P;
+  using LU = typename LatOf<K>::U;
   using T = typename ST::T;
   const typename ST::S *G = reinterpret_cast<const typename ST::S *>(sd.g_in);
   const typename ST::P *Ph = reinterpret_cast<const typename ST::P *>(sd.phi_in);
@@ -315,26 +322,32 @@ __global__ __launch_bounds__(256) void export_kernel(SimDev sd, double *phi, dou
   }
 }
 
-template <int DIM, class ST>
+template <int K, class ST>
 static hipError_t launch_export_t(const SimDev &sd, double *phi, double *u, int16_t *ids, double *g, double *f,
                                   hipStream_t st) {
   const long long total = (long long)sd.nx * sd.nyp * sd.nm;
   long long nb = (total + 255) / 256;
   if (nb > 65536) nb = 65536;
-  hipLaunchKernelGGL((export_kernel<DIM, ST>), dim3((unsigned)nb), dim3(256), 0, st, sd, phi, u, ids, g, f);
+  hipLaunchKernelGGL((export_kernel<K, ST>), dim3((unsigned)nb), dim3(256), 0, st, sd, phi, u, ids, g, f);
   return hipGetLastError();
 }
 
-hipError_t launch_export(int dim, int storage, const SimDev &sd, double *phi, double *u, int16_t *ids, double *g,
-                         double *f, int /*ny_full*/, hipStream_t st) {
-  if (dim == 2) {
-    if (storage == 0) return launch_export_t<2, StF64>(sd, phi, u, ids, g, f, st);
-    if (storage == 1) return launch_export_t<2, StF32>(sd, phi, u, ids, g, f, st);
-    return launch_export_t<2, StF16>(sd, phi, u, ids, g, f, st);
+template <int K>
+static hipError_t launch_export_k(int storage, const SimDev &sd, double *phi, double *u, int16_t *ids, double *g,
+                                  double *f, hipStream_t st) {
+  if (storage == 0) return launch_export_t<K, StF64>(sd, phi, u, ids, g, f, st);
+  if (storage == 1) return launch_export_t<K, StF32>(sd, phi, u, ids, g, f, st);
+  return launch_export_t<K, StF16>(sd, phi, u, ids, g, f, st);
+}
+
+hipError_t launch_export(int lattice, int storage, const SimDev &sd, double *phi, double *u, int16_t *ids,
+                         double *g, double *f, int /*ny_full*/, hipStream_t st) {
+  switch (lattice) {
+    case 0: return launch_export_k<0>(storage, sd, phi, u, ids, g, f, st);
+    case 1: return launch_export_k<1>(storage, sd, phi, u, ids, g, f, st);
+    case 2: return launch_export_k<2>(storage, sd, phi, u, ids, g, f, st);
   }
-  if (storage == 0) return launch_export_t<3, StF64>(sd, phi, u, ids, g, f, st);
-  if (storage == 1) return launch_export_t<3, StF32>(sd, phi, u, ids, g, f, st);
-  return launch_export_t<3, StF16>(sd, phi, u, ids, g, f, st);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace lbpf

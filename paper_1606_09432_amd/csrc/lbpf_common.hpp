@@ -57,13 +57,43 @@ struct D3Q7 {
   static constexpr double INV_E2 = 4.0;
 };
 
+// D3Q15 (Sec. 3.3, Table Values-Lattices): rest 2/9, axes 1/9, the eight cube
+// diagonals 1/72, e^2 = 1/3, in the paper's order of the vectors.
+struct D3Q15 {
+  static constexpr int Q = 15;
+  static constexpr int E[15][3] = {{0, 0, 0},  {1, 0, 0},   {0, 1, 0},    {-1, 0, 0},  {0, -1, 0},
+                                   {0, 0, 1},  {0, 0, -1},  {1, 1, 1},    {-1, 1, 1},  {-1, -1, 1},
+                                   {1, -1, 1}, {1, 1, -1},  {-1, 1, -1},  {-1, -1, -1}, {1, -1, -1}};
+  static constexpr double W[15] = {2.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9,  1.0 / 9,
+                                   1.0 / 9,  1.0 / 9,  1.0 / 72, 1.0 / 72, 1.0 / 72,
+                                   1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72, 1.0 / 72};
+  static constexpr int OPP[15] = {0, 3, 4, 1, 2, 6, 5, 13, 14, 11, 12, 9, 10, 7, 8};
+  static constexpr double INV_E2 = 3.0;
+};
+
+// The heat lattice of a dimension, and the lattice pair of a pair code K
+// (0: D2Q9 + D2Q5, 1: D3Q19 + D3Q7, 2: D3Q15 + D3Q7).
 template <int DIM> struct Lat;
 template <> struct Lat<2> {
-  using P = D2Q9;
   using U = D2Q5;
 };
 template <> struct Lat<3> {
+  using U = D3Q7;
+};
+template <int K> struct LatOf;
+template <> struct LatOf<0> {
+  static constexpr int DIM = 2;
+  using P = D2Q9;
+  using U = D2Q5;
+};
+template <> struct LatOf<1> {
+  static constexpr int DIM = 3;
   using P = D3Q19;
+  using U = D3Q7;
+};
+template <> struct LatOf<2> {
+  static constexpr int DIM = 3;
+  using P = D3Q15;
   using U = D3Q7;
 };
 

@@ -42,17 +42,18 @@ struct InitSrc {
 constexpr int kDiagVals = 6;
 constexpr int kDiagBlocks = 512;
 
-hipError_t launch_step(int dim, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st);
+// lattice: pair code (0 D2Q9/D2Q5, 1 D3Q19/D3Q7, 2 D3Q15/D3Q7).
+hipError_t launch_step(int lattice, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st);
 // sims: the SimDev of every simulation for the step's parity (device memory).
 hipError_t launch_batch(int storage, bool ids, const SimDev *sims, const BatchItem *items, int n_items, int grid,
                         hipStream_t st);
 // Resident work-groups per compute unit of the batch kernel (0 on failure).
 int batch_blocks_per_cu(int storage, bool ids);
-hipError_t launch_init(int dim, int storage, const SimDev &sd, int16_t *ids_out, const InitSrc &src,
+hipError_t launch_init(int lattice, int storage, const SimDev &sd, int16_t *ids_out, const InitSrc &src,
                        hipStream_t st);
 hipError_t launch_diag(int dim, int storage, const SimDev &sd, double *partials, double *result,
                        long long nodes, int ox, int oy, int oz, int dx, int dy, int dz, hipStream_t st);
-hipError_t launch_export(int dim, int storage, const SimDev &sd, double *phi, double *u, int16_t *ids,
+hipError_t launch_export(int lattice, int storage, const SimDev &sd, double *phi, double *u, int16_t *ids,
                          double *g, double *f, int ny_full, hipStream_t st);
 
 }  // namespace lbpf

@@ -70,14 +70,15 @@ template <int DIM, int TY, class ST> constexpr int min_waves() {
 // list `items` of a batched ensemble, whose per-simulation state is sims[k];
 // items are in decreasing cost and work-group b takes items b, b + G, b + 2G,
 // ... (G = grid size): static balance, no atomics, no per-step reset.
-template <int DIM, int TY, class ST, bool IDS, bool BATCH>
-__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(min_waves<DIM, TY, ST>(), 8))) void
+template <int K, int TY, class ST, bool IDS, bool BATCH>
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(min_waves<LatOf<K>::DIM, TY, ST>(), 8))) void
 step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const BatchItem *__restrict__ items,
             int n_items) {
+  constexpr int DIM = LatOf<K>::DIM;
   static_assert(!BATCH || DIM == 2, "batched ensembles are 2D");
   using T = typename ST::T;
-  using LP = typename Lat<DIM>::P;
-  using LU = typename Lat<DIM>::U;
+  using LP = typename LatOf<K>::P;
+  using LU = typename LatOf<K>::U;
   using S = typename ST::S;
   using PT = typename ST::P;
   constexpr int TX = 64;
@@ -590,54 +591,56 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
   }
 }
 
-template <int DIM, int TY, class ST, bool IDS>
+template <int K, int TY, class ST, bool IDS>
 static hipError_t launch_step_t(const SimDev &sd, const TileDev &tc, hipStream_t st) {
   const int nblocks = tc.tiles_x * tc.tiles_y * tc.nchunks;
-  dim3 block(64, DIM == 3 ? TY : 1);
-  hipLaunchKernelGGL((step_kernel<DIM, TY, ST, IDS, false>), dim3(nblocks), block, 0, st, sd, tc, nullptr, nullptr, 0);
+  dim3 block(64, LatOf<K>::DIM == 3 ? TY : 1);
+  hipLaunchKernelGGL((step_kernel<K, TY, ST, IDS, false>), dim3(nblocks), block, 0, st, sd, tc, nullptr, nullptr, 0);
   return hipGetLastError();
 }
 
-template <int DIM, class ST, bool IDS>
+template <int K, class ST, bool IDS>
 static hipError_t launch_step_ty(const SimDev &sd, const TileDev &tc, hipStream_t st) {
-  if constexpr (DIM == 2) {
-    return launch_step_t<2, 1, ST, IDS>(sd, tc, st);
+  if constexpr (LatOf<K>::DIM == 2) {
+    return launch_step_t<K, 1, ST, IDS>(sd, tc, st);
   } else {
     switch (tc.ty) {
-      case 4: return launch_step_t<3, 4, ST, IDS>(sd, tc, st);
+      case 4: return launch_step_t<K, 4, ST, IDS>(sd, tc, st);
       case 8:
-        if constexpr (!std::is_same<ST, StF64>::value) return launch_step_t<3, 8, ST, IDS>(sd, tc, st);
+        if constexpr (!std::is_same<ST, StF64>::value) return launch_step_t<K, 8, ST, IDS>(sd, tc, st);
         return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
     }
   }
 }
 
-template <int DIM, class ST>
+template <int K, class ST>
 static hipError_t launch_step_st(const SimDev &sd, const TileDev &tc, hipStream_t st) {
-  return sd.use_ids ? launch_step_ty<DIM, ST, true>(sd, tc, st) : launch_step_ty<DIM, ST, false>(sd, tc, st);
+  return sd.use_ids ? launch_step_ty<K, ST, true>(sd, tc, st) : launch_step_ty<K, ST, false>(sd, tc, st);
 }
 
-hipError_t launch_step(int dim, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st) {
-  if (dim == 2) {
-    switch (storage) {
-      case 0: return launch_step_st<2, StF64>(sd, tc, st);
-      case 1: return launch_step_st<2, StF32>(sd, tc, st);
-      case 2: return launch_step_st<2, StF16>(sd, tc, st);
-    }
-  } else {
-    switch (storage) {
-      case 0: return launch_step_st<3, StF64>(sd, tc, st);
-      case 1: return launch_step_st<3, StF32>(sd, tc, st);
-      case 2: return launch_step_st<3, StF16>(sd, tc, st);
-    }
+template <int K>
+static hipError_t launch_step_k(int storage, const SimDev &sd, const TileDev &tc, hipStream_t st) {
+  switch (storage) {
+    case 0: return launch_step_st<K, StF64>(sd, tc, st);
+    case 1: return launch_step_st<K, StF32>(sd, tc, st);
+    case 2: return launch_step_st<K, StF16>(sd, tc, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_step(int lattice, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st) {
+  switch (lattice) {
+    case 0: return launch_step_k<0>(storage, sd, tc, st);
+    case 1: return launch_step_k<1>(storage, sd, tc, st);
+    case 2: return launch_step_k<2>(storage, sd, tc, st);
   }
   return hipErrorInvalidValue;
 }
 
 template <class ST, bool IDS>
 static hipError_t launch_batch_t(const SimDev *sims, const BatchItem *items, int n_items, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((step_kernel<2, 1, ST, IDS, true>), dim3(grid), dim3(64), 0, st, SimDev{}, TileDev{}, sims, items,
+  hipLaunchKernelGGL((step_kernel<0, 1, ST, IDS, true>), dim3(grid), dim3(64), 0, st, SimDev{}, TileDev{}, sims, items,
                      n_items);
   return hipGetLastError();
 }
@@ -658,7 +661,7 @@ hipError_t launch_batch(int storage, bool ids, const SimDev *sims, const BatchIt
 
 template <class ST, bool IDS> static int batch_occupancy_t() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<2, 1, ST, IDS, true>, 64, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<0, 1, ST, IDS, true>, 64, 0) != hipSuccess)
     return 0;
   return nb;
 }

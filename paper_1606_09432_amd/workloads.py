@@ -25,7 +25,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-LATTICES = ("D2Q9_D2Q5", "D3Q19_D3Q7")
+LATTICES = ("D2Q9_D2Q5", "D3Q19_D3Q7", "D3Q15_D3Q7")
 BOUNDARIES = ("periodic", "zero_flux")
 GRADIENTS = ("dd", "cd")
 STORAGES = ("fp64", "fp32", "fp16")
@@ -176,11 +176,12 @@ C3_VARIANTS = {
 }
 
 
-def c3(storage: str = "fp16", variant: str = "100", n: int = 512, radius: float = 8.0) -> SimConfig:
+def c3(storage: str = "fp16", variant: str = "100", n: int = 512, radius: float = 8.0,
+       lattice: str = "D3Q19_D3Q7") -> SimConfig:
     (e1, e2), tip = C3_VARIANTS[variant]
     c = n // 2
     return SimConfig(
-        lattice="D3Q19_D3Q7", nx=n, ny=n, nz=n, boundary="zero_flux", gradient="dd",
+        lattice=lattice, nx=n, ny=n, nz=n, boundary="zero_flux", gradient="dd",
         storage=storage, delta=0.6, kappa=KAPPA_C0,
         aniso=[Aniso("cubic_hak", eps=e1, gamma=e2)],
         seeds=[Seed(c, c, c, radius, 1)], tip_dir=tip)

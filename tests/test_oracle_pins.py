@@ -24,7 +24,7 @@ GOLD = json.load(open(os.path.join(HERE, "golden", "paper_values.json")))
 # ---------------------------------------------------------------------------
 # P1: lattice tables (Sec. 3.3, Table Values-Lattices) and moment identities.
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("name", ["D2Q5", "D2Q9", "D3Q7"])
+@pytest.mark.parametrize("name", ["D2Q5", "D2Q9", "D3Q7", "D3Q15"])
 def test_lattice_tables_match_paper(oracle_mod, name):
     e, w, opp, e2 = oracle_mod.lattice(name)
     g = GOLD["lattices"][name]
@@ -36,7 +36,7 @@ def test_lattice_tables_match_paper(oracle_mod, name):
     assert e2 == float(Fraction(g["e2"]))
 
 
-@pytest.mark.parametrize("name", ["D2Q5", "D2Q9", "D3Q7", "D3Q19"])
+@pytest.mark.parametrize("name", ["D2Q5", "D2Q9", "D3Q7", "D3Q19", "D3Q15"])
 def test_lattice_moment_identities(oracle_mod, name):
     e, w, opp, e2 = oracle_mod.lattice(name)
     wf = [Fraction(x).limit_denominator(1000) for x in w]
@@ -51,7 +51,7 @@ def test_lattice_moment_identities(oracle_mod, name):
             assert m2 == expect, (a, b, m2)
     for i in range(len(w)):
         assert (e[opp[i]] == -e[i]).all()
-    if name in ("D2Q9", "D3Q19"):
+    if name in ("D2Q9", "D3Q19", "D3Q15"):
         # fourth-order isotropy needed by the phase-field lattice
         m4 = sum(wi * int(ei[0]) ** 4 for wi, ei in zip(wf, e))
         m22 = sum(wi * int(ei[0]) ** 2 * int(ei[1]) ** 2 for wi, ei in zip(wf, e))
@@ -74,14 +74,16 @@ def _smooth_field(shape, seed=3):
     return f
 
 
-@pytest.mark.parametrize("lattice,shape", [("D2Q9_D2Q5", (20, 24)), ("D3Q19_D3Q7", (8, 10, 12))])
+@pytest.mark.parametrize("lattice,shape", [("D2Q9_D2Q5", (20, 24)), ("D3Q19_D3Q7", (8, 10, 12)),
+                                           ("D3Q15_D3Q7", (8, 10, 12))])
 def test_equilibrium_moments(oracle_mod, lattice, shape):
     if lattice == "D2Q9_D2Q5":
         cfg = W.c0(n=24).replace(ny=20, nx=24, aniso=[W.Aniso("sectoral", 0.05, 4, 0.3)])
         ename = "D2Q9"
     else:
         cfg = W.small_3d(nx=12, ny=10, nz=8, aniso=W.Aniso("cubic_hak", eps=0.1, gamma=-0.02))
-        ename = "D3Q19"
+        cfg = cfg.replace(lattice=lattice)
+        ename = lattice.split("_")[0]
     sim = oracle_mod.OracleSim(cfg)
     phi = 0.8 * np.tanh(_smooth_field(shape) * 3)
     u = -0.3 + 0.1 * _smooth_field(shape, seed=5)
@@ -171,6 +173,28 @@ def test_dd_closed_form_d3q19(oracle_mod):
     pz = (s(0, 0, 1) - s(0, 0, -1)) / 6 + (
         s(1, 0, 1) + s(-1, 0, 1) + s(0, 1, 1) + s(0, -1, 1)
         - s(1, 0, -1) - s(-1, 0, -1) - s(0, 1, -1) - s(0, -1, -1)) / 12
+    np.testing.assert_allclose(p[..., 0], px, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(p[..., 2], pz, rtol=0, atol=1e-15)
+
+
+def test_dd_closed_form_d3q15(oracle_mod):
+    """DD gradient on D3Q15: p_x = (E - W)/3 + (1/24) sum over the four cube
+    diagonals c with c_x = +1 of [phi(x + c) - phi(x - c)]."""
+    cfg = W.small_3d(n=8).replace(boundary="periodic", lattice="D3Q15_D3Q7")
+    sim = oracle_mod.OracleSim(cfg)
+    assert sim.q_phi == 15
+    rng = np.random.default_rng(7)
+    phi = rng.uniform(-1, 1, size=(8, 8, 8))
+    sim.set_fields(phi, np.zeros_like(phi))
+    p = sim.params()["p"]
+
+    def s(dx, dy, dz):
+        return np.roll(phi, (-dz, -dy, -dx), axis=(0, 1, 2))
+
+    corners = [(1, a, b) for a in (-1, 1) for b in (-1, 1)]
+    px = (s(1, 0, 0) - s(-1, 0, 0)) / 3 + sum(s(*c) - s(*[-v for v in c]) for c in corners) / 24
+    zc = [(a, b, 1) for a in (-1, 1) for b in (-1, 1)]
+    pz = (s(0, 0, 1) - s(0, 0, -1)) / 3 + sum(s(*c) - s(*[-v for v in c]) for c in zc) / 24
     np.testing.assert_allclose(p[..., 0], px, rtol=0, atol=1e-15)
     np.testing.assert_allclose(p[..., 2], pz, rtol=0, atol=1e-15)
 
@@ -386,7 +410,7 @@ def test_gaussian_matches_continuum(oracle_mod):
 # P9: step order and coupling — sum(u - phi/2) is conserved on periodic boxes
 # (Q_u dt = (phi^{n+1} - phi^n)/2 after the phase-field step, Sec. 3.1).
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("case", ["2d", "3d"])
+@pytest.mark.parametrize("case", ["2d", "3d", "3d_q15"])
 def test_conservation_periodic(oracle_mod, case):
     if case == "2d":
         cfg = W.c0(n=64)
@@ -394,6 +418,8 @@ def test_conservation_periodic(oracle_mod, case):
         steps = 300
     else:
         cfg = W.small_3d(n=20, boundary="periodic", radius=5.0)
+        if case == "3d_q15":
+            cfg = cfg.replace(lattice="D3Q15_D3Q7")
         steps = 40
     sim = oracle_mod.OracleSim(cfg)
     c0 = sim.diagnostics()["sum_u_minus_half_phi"]
@@ -482,10 +508,11 @@ def test_rotation_invariance_2d(oracle_mod, grad, boundary):
     assert np.abs(sim.phi() - sim.phi()[::-1, :]).max() > 1e-6  # theta0 = 20 deg breaks mirror symmetry
 
 
+@pytest.mark.parametrize("lattice", ["D3Q19_D3Q7", "D3Q15_D3Q7"])
 @pytest.mark.parametrize("entry", [W.Aniso("cubic_hak", eps=0.0, gamma=-0.05), W.Aniso("sectoral", 0.05, 4, 0.3)])
-def test_rotation_invariance_3d(oracle_mod, entry):
+def test_rotation_invariance_3d(oracle_mod, entry, lattice):
     n = 21
-    cfg = W.small_3d(n=n, aniso=entry, radius=4.0)
+    cfg = W.small_3d(n=n, aniso=entry, radius=4.0).replace(lattice=lattice)
     sim = oracle_mod.OracleSim(cfg)
     sim.step(25)
     c = n // 2
