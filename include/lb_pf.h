@@ -175,8 +175,8 @@ int lb_pf_state_bytes(const lbpf_handle *h, size_t *bytes);
 int lb_pf_save_state(lbpf_handle *h, void *dev_buf, size_t bytes, void *hip_stream);
 int lb_pf_load_state(lbpf_handle *h, const void *dev_buf, size_t bytes, void *hip_stream);
 
-/* Tile shape of the step kernel: tile_y (4 or 8; 8 needs FP32 arithmetic) rows
- * of 64 nodes per work-group in 3D (1 in 2D), and `chunk` planes marched per
+/* Tile shape of the step kernel: tile_y (4, 8 or 12; 8 and 12 need FP32
+ * arithmetic) rows of 64 nodes per work-group in 3D (1 in 2D), and `chunk` planes marched per
  * work-group (rows per work item, at least 8, for a batched handle).  0 keeps
  * the current value.  lb_pf_autotune times the candidate shapes on hip_stream
  * (advancing the state by the steps it runs: three times steps_per_trial per

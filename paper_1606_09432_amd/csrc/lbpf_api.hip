@@ -138,15 +138,24 @@ void units(const lbpf_config &c, SimHost &s) {
   s.width = std::sqrt(2.0) * (c.W0 / c.dx);
 }
 
+// Default tile, from measurements at 512^3: FP64 (256 VGPRs, two work-groups
+// of 4 x 64 per CU) 4 rows; FP32 arithmetic 12 rows (one work-group of 12
+// waves per CU, 3 per SIMD: the 2-node halo of the coefficient pass then costs
+// 1/3 of what it costs at 4 rows).  3D: 32 planes per work-group, fewer when
+// that would leave fewer than 2048 work-groups.  2D: about 16384 work-groups,
+// at least 16 rows each.
 void default_tile(SimHost &s) {
   TileDev &t = s.tile;
-  t.ty = s.dim == 3 ? (s.storage == LBPF_FP64 ? 4 : 4) : 1;
+  t.ty = s.dim == 3 ? (s.storage == LBPF_FP64 ? 4 : 12) : 1;
   t.tiles_x = (s.nx + 63) / 64;
   t.tiles_y = s.dim == 3 ? (s.nyp + t.ty - 1) / t.ty : 1;
   const long long tiles = (long long)t.tiles_x * t.tiles_y;
-  const long long target = 16384;  // work-groups per launch: 16 x 1024 for 512^3
-  long long ch = (s.nm * tiles + target - 1) / target;
-  ch = std::max<long long>(ch, s.dim == 3 ? 16 : 16);
+  long long ch;
+  if (s.dim == 3) {
+    ch = std::min<long long>(32, std::max<long long>(8, s.nm * tiles / 2048));
+  } else {
+    ch = std::max<long long>(16, (s.nm * tiles + 16383) / 16384);
+  }
   ch = std::min<long long>(ch, s.nm);
   t.chunk = (int)ch;
   t.nchunks = (s.nm + t.chunk - 1) / t.chunk;
@@ -156,8 +165,10 @@ int set_tile(SimHost &s, int ty, int chunk) {
   TileDev t = s.tile;
   if (ty > 0) {
     if (s.dim == 2 && ty != 1) return fail(LBPF_ERR_UNSUPPORTED, "2D tiles are one row high");
-    if (s.dim == 3 && ty != 4 && ty != 8) return fail(LBPF_ERR_UNSUPPORTED, "tile_y must be 4 or 8");
-    if (s.dim == 3 && ty == 8 && s.storage == LBPF_FP64) return fail(LBPF_ERR_UNSUPPORTED, "tile_y 8 needs FP32 arithmetic");
+    if (s.dim == 3 && ty != 4 && ty != 8 && ty != 12)
+      return fail(LBPF_ERR_UNSUPPORTED, "tile_y must be 4, 8 or 12");
+    if (s.dim == 3 && ty != 4 && s.storage == LBPF_FP64)
+      return fail(LBPF_ERR_UNSUPPORTED, "tile_y above 4 needs FP32 arithmetic");
     t.ty = ty;
   }
   if (chunk > 0) t.chunk = std::min(chunk, s.nm);
@@ -666,7 +677,7 @@ int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream) {
   if (steps_per_trial < 1) return fail(LBPF_ERR_ARG, "steps_per_trial < 1");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const SimHost &s0 = h->sims[0];
-  std::vector<int> tys = s0.dim == 3 ? std::vector<int>{4, 8} : std::vector<int>{1};
+  std::vector<int> tys = s0.dim == 3 ? std::vector<int>{4, 8, 12} : std::vector<int>{1};
   std::vector<int> chunks = s0.dim == 3 ? std::vector<int>{16, 32, 64, 128} : std::vector<int>{16, 32, 64, 128};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -674,7 +685,7 @@ int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream) {
   float best = 1e30f;
   int bty = s0.tile.ty, bch = h->batch.on ? h->batch.chunk : s0.tile.chunk;
   for (int ty : tys) {
-    if (s0.dim == 3 && ty == 8 && s0.storage == LBPF_FP64) continue;
+    if (s0.dim == 3 && ty != 4 && s0.storage == LBPF_FP64) continue;
     for (int ch : chunks) {
       if (lb_pf_set_tile(h, ty, ch)) continue;
       // warm-up of twice the trial: the trial then starts from the same

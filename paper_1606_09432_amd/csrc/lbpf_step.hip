@@ -609,6 +609,9 @@ static hipError_t launch_step_ty(const SimDev &sd, const TileDev &tc, hipStream_
       case 8:
         if constexpr (!std::is_same<ST, StF64>::value) return launch_step_t<K, 8, ST, IDS>(sd, tc, st);
         return hipErrorInvalidValue;
+      case 12:
+        if constexpr (!std::is_same<ST, StF64>::value) return launch_step_t<K, 12, ST, IDS>(sd, tc, st);
+        return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
     }
   }

@@ -229,7 +229,7 @@ def test_3d_offset_storage_accuracy(gpu, oracle_mod, storage, tol):
 # Launch shape, determinism, checkpoint, batching.
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("storage,tiles", [("fp64", [(4, 8), (4, 64), (4, 5)]),
-                                           ("fp16", [(4, 16), (4, 7), (8, 64)])])
+                                           ("fp16", [(12, 32), (4, 7), (8, 64), (12, 5), (12, 9)])])
 def test_tile_shapes_bitwise_equal(gpu, storage, tiles):
     cfg = W.small_3d(storage=storage, nx=70, ny=37, nz=29, radius=6)
     outs = []
