@@ -413,7 +413,7 @@ def main():
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "launches": 3}), flush=True)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the z-slab sharding is a "
+        print("bench.py measures one GPU: there is no multi-GPU path (the z-slab sharding is a "
               "design note only); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

@@ -56,7 +56,7 @@ extern "C" {
 #define LBPF_ERR_WORKSPACE (-3)   /* workspace NULL, misaligned or too small */
 #define LBPF_ERR_HIP (-4)         /* a HIP runtime call failed */
 #define LBPF_ERR_NONFINITE (-5)   /* diagnostics found a non-finite phi or u */
-#define LBPF_ERR_UNSUPPORTED (-6) /* valid request this build does not implement */
+#define LBPF_ERR_UNSUPPORTED (-6) /* valid request the library does not implement */
 
 /* Lattice pairs (Sec. 3.3): phi lattice + u lattice.  D3Q15 is the paper's own
  * 3D phi lattice (Table Values-Lattices); D3Q19 takes the standard weights
