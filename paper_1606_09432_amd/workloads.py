@@ -230,6 +230,20 @@ def e2(gradient: str = "dd", n: int = 800, storage: str = "fp64") -> SimConfig:
 E2_STEPS = 100000
 
 
+def multi_3d(storage: str = "fp64", lattice: str = "D3Q19_D3Q7", gradient: str = "dd",
+             shape=(48, 44, 40), boundary: str = "zero_flux") -> SimConfig:
+    """A small 3D box with three crystals, each with its own anisotropy entry
+    in the crystal index field (Sec. 4.3): cubic, Eq. As_MatSci and Eq. As_Y66."""
+    nx, ny, nz = shape
+    aniso = [Aniso("iso"), Aniso("cubic", eps=0.05), Aniso("cubic_hak", eps=0.1, gamma=0.0),
+             Aniso("sectoral", eps=0.05, q=6, phi0=0.3)]
+    seeds = [Seed(nx * 0.27, ny * 0.3, nz * 0.35, 4.0, 1), Seed(nx * 0.7, ny * 0.33, nz * 0.6, 4.5, 2),
+             Seed(nx * 0.45, ny * 0.72, nz * 0.5, 3.5, 3)]
+    return SimConfig(
+        lattice=lattice, nx=nx, ny=ny, nz=nz, boundary=boundary, gradient=gradient, storage=storage,
+        delta=0.55, kappa=KAPPA_C0, aniso=aniso, seeds=seeds, use_ids=True, tip_dir=(1, 0, 0))
+
+
 def small_3d(storage: str = "fp64", n: int = 48, aniso: Aniso | None = None,
              boundary: str = "zero_flux", radius: float = 6.0, delta: float = 0.55,
              nx: int | None = None, ny: int | None = None, nz: int | None = None) -> SimConfig:

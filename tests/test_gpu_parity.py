@@ -159,6 +159,54 @@ def test_crystal_index_parity(gpu, oracle_mod, grad):
     _compare(gpu, oracle_mod, cfg, 300)
 
 
+@pytest.mark.parametrize("lattice,grad,boundary", [("D3Q19_D3Q7", "dd", "zero_flux"), ("D3Q19_D3Q7", "cd", "periodic"),
+                                                  ("D3Q15_D3Q7", "dd", "zero_flux")])
+def test_3d_crystal_index_parity(gpu, oracle_mod, lattice, grad, boundary):
+    """Three crystals with different anisotropy entries in the 3D index field."""
+    cfg = W.multi_3d(lattice=lattice, gradient=grad, boundary=boundary)
+    sim, orc = _compare(gpu, oracle_mod, cfg, 120)
+    ids = orc.ids()
+    assert all((ids == k).sum() > 300 for k in (1, 2, 3))  # every crystal grew
+
+
+@pytest.mark.parametrize("storage,tol", [("fp32", 1e-4), ("fp16", 2e-3)])
+def test_3d_crystal_index_offset_storage(gpu, oracle_mod, storage, tol):
+    """Offset storage with the index field: phi and u within the offset bounds.
+    The index decisions are taken in FP32 there (the oracle takes them in
+    FP64).  At the outer edge of the dilation, |grad phi| is compared with
+    xi = 1e-7 where phi is within 1e-6 of -1, i.e. at the FP32 rounding level
+    of phi, so those decisions may differ; wherever phi > -0.99 the index must
+    agree exactly, and the far-field differences stay below 0.1 % of the nodes."""
+    cfg = W.multi_3d(storage=storage)
+    _say(_case(cfg, 120))
+    sim, phi, u, ids = _gpu_run(gpu, cfg, 120)
+    orc = _oracle_run(oracle_mod, cfg, 120)
+    ephi = np.abs(phi - orc.phi()).max()
+    eu = np.abs(u - orc.u()).max()
+    diff = ids != orc.ids()
+    near = diff & (orc.phi() > -0.99)
+    _say(f"  {storage}: max|dphi| = {ephi:.3e} max|du| = {eu:.3e} index mismatches {int(diff.sum())} "
+         f"(near the crystals {int(near.sum())})")
+    assert ephi <= tol and eu <= tol
+    assert int(near.sum()) == 0 and int(diff.sum()) <= cfg.nodes // 1000
+
+
+def test_batched_with_index_field(gpu, oracle_mod):
+    """A batched ensemble whose members use the crystal index field."""
+    cfgs = [W.c1(n=n, count=3, rng_seed=s).replace(ny=n + 16) for n, s in ((96, 1), (128, 2), (80, 3))]
+    _say("batched ensemble with index fields, 60 steps")
+    sim = gpu.Simulation(cfgs)
+    sim.step(60)
+    for k, cfg in enumerate(cfgs):
+        phi, u, ids = sim.fields(k)
+        orc = _oracle_run(oracle_mod, cfg, 60)
+        ep = np.abs(phi.cpu().numpy() - orc.phi()).max()
+        eu = np.abs(u.cpu().numpy() - orc.u()).max()
+        bad = int((ids.cpu().numpy() != orc.ids()).sum())
+        _say(f"  sim {k}: max|dphi| = {ep:.3e} max|du| = {eu:.3e} index mismatches {bad}")
+        assert ep <= FP64_TOL and eu <= FP64_TOL and bad == 0
+
+
 def test_c1_full_size_parity(gpu, oracle_mod):
     """2048^2 with 20 crystals, in the default launch configuration, elementwise."""
     _compare(gpu, oracle_mod, W.c1(), 12)
