@@ -61,7 +61,7 @@ struct BatchState {
   bool on = false;
   bool ids = false;
   int storage = 0;
-  int chunk = 32;
+  int chunk = 8;                       // rows per work item (measured best for the 256-member ensemble)
   size_t off_sims = 0, off_items = 0;  // workspace offsets
   int max_items = 0;
   std::vector<SimDev> tables;          // [parity][sim]
@@ -143,7 +143,7 @@ void units(const lbpf_config &c, SimHost &s) {
 // waves per CU, 3 per SIMD: the 2-node halo of the coefficient pass then costs
 // 1/3 of what it costs at 4 rows).  3D: 32 planes per work-group, fewer when
 // that would leave fewer than 2048 work-groups.  2D: about 16384 work-groups,
-// at least 16 rows each.
+// at least 16 rows each (8 in FP64).
 void default_tile(SimHost &s) {
   TileDev &t = s.tile;
   t.ty = s.dim == 3 ? (s.storage == LBPF_FP64 ? 4 : 12) : 1;
@@ -154,7 +154,7 @@ void default_tile(SimHost &s) {
   if (s.dim == 3) {
     ch = std::min<long long>(32, std::max<long long>(8, s.nm * tiles / 2048));
   } else {
-    ch = std::max<long long>(16, (s.nm * tiles + 16383) / 16384);
+    ch = std::max<long long>(s.storage == LBPF_FP64 ? 8 : 16, (s.nm * tiles + 16383) / 16384);
   }
   ch = std::min<long long>(ch, s.nm);
   t.chunk = (int)ch;
@@ -678,7 +678,7 @@ int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream) {
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const SimHost &s0 = h->sims[0];
   std::vector<int> tys = s0.dim == 3 ? std::vector<int>{4, 8, 12} : std::vector<int>{1};
-  std::vector<int> chunks = s0.dim == 3 ? std::vector<int>{16, 32, 64, 128} : std::vector<int>{16, 32, 64, 128};
+  std::vector<int> chunks = s0.dim == 3 ? std::vector<int>{16, 32, 64, 128} : std::vector<int>{8, 16, 32, 64};
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));

@@ -387,7 +387,7 @@ def test_batched_autotune_and_chunks(gpu):
     sim = gpu.Simulation(cfgs)
     sim.autotune(2)
     ty, ch = sim.get_tile()
-    assert ty == 1 and ch in (16, 32, 64, 128)
+    assert ty == 1 and ch in (8, 16, 32, 64)
     sim.set_tile(1, 8)
     sim.step(5)
     sim.set_tile(1, 128)
