@@ -1,9 +1,9 @@
 // Fused coupled step (phase field, then heat) for gfx950.
 //
 // One launch advances one simulation (or, in 2D, a batch of them) by one time
-// step.  A work-group owns a
-// 64 x TY tile of the plane perpendicular to the march axis m (z in 3D, y in
-// 2D; TY = 1 in 2D) and walks `chunk` planes along m.  For output plane m it
+// step.  A work-group owns a 64 x TY tile of the plane perpendicular to the
+// march axis m (z in 3D, y in 2D; TY = 1 in 2D) and walks `chunk` planes along
+// m.  For output plane m it
 //   A. computes, for plane m+1 on the tile + 1-node halo, the gradient of
 //      phi^n (directional derivatives, Eqs. Def_DeriveeDirectionnelle and
 //      Grad_DF-Centree, or central differences), the crystal index update
@@ -25,10 +25,11 @@
 // iteration and land while A runs from LDS and registers; B issues its g
 // loads in one batch.  Index and boundary logic is branch-free (selects) so
 // that loads are never serialised behind branches.  Two work-group barriers
-// per plane.  Every distribution is read
-// from HBM once and written once per step; the shifted read of g_i(x) and
-// the halo gathers hit L2.  Tiles whose halo stays inside the box take a path
-// without boundary checks.
+// per plane.  Every distribution is written once per step and loaded once as
+// the node's own value; the shifted load of g_i(x), the heat gathers of the
+// halo nodes and the ring halos are the extra loads, served by L2 only in
+// part (the rest shows as HBM traffic above the algorithmic bytes).  Tiles
+// whose halo stays inside the box take a path without boundary checks.
 //
 // Offset storage (FP32 arithmetic): h_i = g_i - w_i phi and
 // k_i = f*_i - w_i u* are stored in FP32 or FP16 beside FP32 phi and u*; the
