@@ -358,7 +358,8 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, 
                               "bytes_per_node": (rb + wb) / nodes}
         md.append(f"| `{k}` | {f:.0f} | {w:.0f} | {rb:.4g} | {wb:.4g} | {rb + wb:.4g} | "
                   f"{(rb + wb) / nodes:.1f} |")
-    md += ["", f"Kernel source hash: {sha} (bench.py reports this traffic only while it matches)."]
+    md += ["", f"Kernel source hash: {sha} (comments and blank lines excluded; bench.py reports this traffic only "
+               "while it matches)."]
     return res, "\n".join(md) + "\n"
 
 
