@@ -68,6 +68,9 @@ def test_workspace_pads_rows_to_64(lib):
 @pytest.mark.parametrize("mutate,code", [
     (dict(nx=2), -1), (dict(lattice="D3Q19_D3Q7", nz=1), -1), (dict(dt=0.0), -2), (dict(W0=-1.0), -1),
     (dict(aniso=[]), -1), (dict(use_ids=True), -1),
+    # one FP32 field of 4 GiB or more cannot be addressed with 32-bit byte offsets
+    (dict(lattice="D3Q19_D3Q7", nx=1024, ny=1024, nz=1024, storage="fp16"), -1),
+    (dict(lattice="D3Q19_D3Q7", nx=1024, ny=1024, nz=512, storage="fp64"), -1),
 ])
 def test_invalid_configs_rejected(lib, mutate, code):
     cfg = W.c0(n=32).replace(**mutate)

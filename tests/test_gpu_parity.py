@@ -243,6 +243,36 @@ def test_c3_full_size_window(gpu, oracle_mod, storage, tol):
     assert ephi <= tol and eu <= tol
 
 
+# The largest grids the 32-bit byte offsets allow (one field just below 4 GiB),
+# with the crystal at the far corner so that the work happens at the largest
+# offsets; a window at that corner is checked against the oracle on a box that
+# shares the two far walls, away from its artificial near walls.
+@pytest.mark.parametrize("storage,shape,tol", [("fp16", (1024, 1024, 1023), 2e-3),
+                                               ("fp64", (1024, 1024, 384), FP64_TOL)])
+def test_maximum_size_far_corner(gpu, oracle_mod, storage, shape, tol):
+    import torch
+    nx, ny, nz = shape
+    k, w = 6, 40
+    cfg = W.small_3d(storage=storage, nx=nx, ny=ny, nz=nz, radius=6.0)
+    cfg.seeds = [W.Seed(nx - 14, ny - 14, nz - 14, 6.0, 1)]
+    _say(_case(cfg, k) + " (largest offsets, far-corner window)")
+    sim = gpu.Simulation(cfg)
+    sim.step(k)
+    phi, u, _ = sim.fields()
+    gphi = phi[nz - w:, ny - w:, nx - w:].cpu().numpy()
+    gu = u[nz - w:, ny - w:, nx - w:].cpu().numpy()
+    del sim, phi, u
+    torch.cuda.empty_cache()
+    wcfg = cfg.replace(nx=w, ny=w, nz=w, storage="fp64", seeds=[W.Seed(w - 14, w - 14, w - 14, 6.0, 1)])
+    orc = _oracle_run(oracle_mod, wcfg, k)
+    inner = slice(2 * k, w)
+    ephi = np.abs(gphi[inner, inner, inner] - orc.phi()[inner, inner, inner]).max()
+    eu = np.abs(gu[inner, inner, inner] - orc.u()[inner, inner, inner]).max()
+    _say(f"  corner window max|dphi| = {ephi:.3e}  max|du| = {eu:.3e}")
+    assert ephi <= tol and eu <= tol
+    assert np.abs(orc.phi()[inner, inner, inner] + 1).max() > 0.5  # the crystal is inside the window
+
+
 # ---------------------------------------------------------------------------
 # Offset storage (FP32 arithmetic, FP32 / FP16 offsets) against the FP64 oracle.
 # ---------------------------------------------------------------------------
