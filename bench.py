@@ -251,6 +251,23 @@ def run_isotropy(steps: int, storage: str):
     return out
 
 
+def run_paper3d(steps: int, warmup: int):
+    """The paper's own 3D runs (D3Q15, 351^3, dendrites A, B, C) timed here, next
+    to the wall-clock times the paper gives for them on 100 CPU cores."""
+    from paper_1606_09432_amd import workloads as W
+
+    out = []
+    for d, (_entry, paper_steps, paper_seconds) in W.PAPER3D.items():
+        for st in ("fp64", "fp16"):
+            cfg = W.paper3d(d, st)
+            r = run_gpu(cfg, steps, warmup, False)
+            out.append({"dendrite": d, "storage": st, "MLUPS": r["value"], "ms_per_step": r["ms_per_step"],
+                        "paper_steps": paper_steps, "time_for_paper_steps_s": r["ms_per_step"] * paper_steps / 1e3,
+                        "paper_wall_clock_s": paper_seconds, "paper_hardware": "100 CPU cores (unnamed cluster)",
+                        "paper_MLUPS": cfg.nodes * paper_steps / paper_seconds / 1e6})
+    return out
+
+
 def cpu_baseline(cfg_full, sample_n: int, sample_steps: int):
     """The CPU FP64 oracle on a bounded sample: the same parameters on a
     sample_n^3 box around the seed, sample_steps steps."""
@@ -379,6 +396,8 @@ def main():
     ap.add_argument("--no-d3q15", action="store_true", help="skip the D3Q15 runs")
     ap.add_argument("--accuracy", choices=["c2", "c3"], default=None,
                     help="only report the FP32/FP16-offset error against FP64 over a run")
+    ap.add_argument("--paper3d", action="store_true",
+                    help="only time the paper's 351^3 D3Q15 runs (context for its wall-clock times)")
     ap.add_argument("--isotropy", type=int, default=0, metavar="STEPS",
                     help="only run the six-fold DD/CD isotropy comparison for STEPS steps")
     ap.add_argument("--acc-steps", type=int, default=2000)
@@ -401,6 +420,10 @@ def main():
         res, md = summarize_traffic(*args.summarize_traffic, args.copy_mib * (1 << 20), args.command)
         json.dump(res, open(TRAFFIC_FILE, "w"), indent=1)
         open(args.out, "w").write(md) if args.out else print(md)
+        return
+    if args.paper3d:
+        for row in run_paper3d(args.steps, args.warmup):
+            print(json.dumps(row), flush=True)
         return
     if args.isotropy:
         print(json.dumps(run_isotropy(args.isotropy, args.only or "fp64")), flush=True)

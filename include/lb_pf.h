@@ -81,12 +81,14 @@ extern "C" {
 #define LBPF_ANISO_SECTORAL 1  /* 1 + eps Re[((n_x + i n_y) e^{-i phi0})^q]: Eq. As_Theta / As_Multi in 2D, Eq. As_Y66 in 3D (q = 6) */
 #define LBPF_ANISO_CUBIC 2     /* 1 - 3 eps + 4 eps (n_x^4 + n_y^4 + n_z^4): Eq. As_Function_Classical */
 #define LBPF_ANISO_CUBIC_HAK 3 /* 1 + eps (Q - 3/5) + gamma (3 Q + 66 S - 17/7): Eq. As_MatSci */
+#define LBPF_ANISO_CUBIC_S 4   /* 1 + 66 gamma n_x^2 n_y^2 n_z^2: Eq. As_Function_S, read with the
+                                  constant 1 (the printed 66 gamma S vanishes on the axes) */
 
 typedef struct {
   int32_t kind;
   int32_t q;     /* sectoral order, >= 1 */
   double eps;
-  double gamma;  /* CUBIC_HAK only */
+  double gamma;  /* CUBIC_HAK and CUBIC_S */
   double phi0;   /* sectoral reference angle, radians */
 } lbpf_aniso;
 

@@ -237,6 +237,15 @@ void orc_aniso_eval(const orc_aniso *an, const double n[3], double *a, double G[
     G[2] = 16.0 * eps * (z2 * nz);
     return;
   }
+  if (an->kind == ORC_ANISO_CUBIC_S) {
+    /* Eq. As_Function_S read as 1 + 66 gamma S, S = n_x^2 n_y^2 n_z^2 */
+    const double gam = an->gamma;
+    *a = 1.0 + 66.0 * gam * ((x2 * y2) * z2);
+    G[0] = 66.0 * gam * (2.0 * nx * (y2 * z2));
+    G[1] = 66.0 * gam * (2.0 * ny * (x2 * z2));
+    G[2] = 66.0 * gam * (2.0 * nz * (x2 * y2));
+    return;
+  }
   /* ORC_ANISO_CUBIC_HAK, Eq. As_MatSci: 1 + eps (Q - 3/5) + gamma (3Q + 66 S - 17/7) */
   const double eps = an->eps, gam = an->gamma;
   const double S = (x2 * y2) * z2;
@@ -634,7 +643,7 @@ int orc_create(const orc_config *cfg, orc_sim **out) {
   if (cfg->n_aniso < 1 || cfg->aniso == NULL) return -1;
   for (int k = 0; k < cfg->n_aniso; ++k) {
     const int kd = cfg->aniso[k].kind;
-    if (kd < 0 || kd > 3) return -1;
+    if (kd < 0 || kd > 4) return -1;
     if (kd == ORC_ANISO_SECTORAL && cfg->aniso[k].q < 1) return -1;
   }
   if (cfg->use_ids && cfg->aniso[0].kind != ORC_ANISO_ISO) return -1;

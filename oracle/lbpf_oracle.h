@@ -28,7 +28,8 @@ enum {
   ORC_ANISO_SECTORAL = 1, /* 1 + eps Re[((n_x + i n_y) e^{-i phi0})^q]: Eq. As_Theta in  */
                           /* 2D (|n| = 1), Eq. As_Multi per crystal, Eq. As_Y66 in 3D   */
   ORC_ANISO_CUBIC = 2,    /* 1 - 3 eps + 4 eps sum n^4: Eq. As_Function_Classical       */
-  ORC_ANISO_CUBIC_HAK = 3 /* 1 + eps (Q - 3/5) + gamma (3Q + 66 S - 17/7): Eq. As_MatSci */
+  ORC_ANISO_CUBIC_HAK = 3, /* 1 + eps (Q - 3/5) + gamma (3Q + 66 S - 17/7): Eq. As_MatSci */
+  ORC_ANISO_CUBIC_S = 4    /* 1 + 66 gamma n_x^2 n_y^2 n_z^2: Eq. As_Function_S (printed without the 1) */
 };
 
 typedef struct {

@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBPF_ORACLE_LIB", os.path.join(HERE, "liblbpf_oracle.so"))
 
-_KIND = {"iso": 0, "sectoral": 1, "cubic": 2, "cubic_hak": 3}
+_KIND = {"iso": 0, "sectoral": 1, "cubic": 2, "cubic_hak": 3, "cubic_s": 4}
 
 
 class OrcAniso(C.Structure):

@@ -107,7 +107,7 @@ int validate(const lbpf_config &c) {
   if (c.n_aniso < 1 || c.n_aniso > kMaxAniso || !c.aniso) return fail(LBPF_ERR_ARG, "need 1..256 anisotropy entries");
   for (int k = 0; k < c.n_aniso; ++k) {
     const lbpf_aniso &a = c.aniso[k];
-    if (a.kind < LBPF_ANISO_ISO || a.kind > LBPF_ANISO_CUBIC_HAK) return fail(LBPF_ERR_ARG, "unknown anisotropy kind");
+    if (a.kind < LBPF_ANISO_ISO || a.kind > LBPF_ANISO_CUBIC_S) return fail(LBPF_ERR_ARG, "unknown anisotropy kind");
     if (a.kind == LBPF_ANISO_SECTORAL && (a.q < 1 || a.q > 64)) return fail(LBPF_ERR_ARG, "sectoral q must be 1..64");
     if (!std::isfinite(a.eps) || !std::isfinite(a.gamma) || !std::isfinite(a.phi0))
       return fail(LBPF_ERR_ARG, "anisotropy parameters must be finite");

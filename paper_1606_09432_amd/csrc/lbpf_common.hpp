@@ -142,7 +142,7 @@ struct AnisoDev {
 };
 constexpr int kMaxAniso = 256;
 
-enum { K_ISO = 0, K_SECTORAL = 1, K_CUBIC = 2, K_CUBIC_HAK = 3 };
+enum { K_ISO = 0, K_SECTORAL = 1, K_CUBIC = 2, K_CUBIC_HAK = 3, K_CUBIC_S = 4 };
 
 // Everything a kernel needs to know about one simulation and one A->B step.
 struct SimDev {
@@ -238,6 +238,15 @@ __device__ __forceinline__ void aniso_eval(const AnisoDev &A, T nx, T ny, T nz, 
     Gx = eps * dQx + gam * (T(3) * dQx + T(66) * dSx);
     Gy = eps * dQy + gam * (T(3) * dQy + T(66) * dSy);
     Gz = eps * dQz + gam * (T(3) * dQz + T(66) * dSz);
+    return;
+  }
+  if (A.kind == K_CUBIC_S) {
+    // Eq. As_Function_S with the constant 1 (1 + 66 gamma S)
+    const T g66 = T(66) * T(A.gamma);
+    a = T(1) + g66 * ((x2 * y2) * z2);
+    Gx = g66 * (T(2) * nx * (y2 * z2));
+    Gy = g66 * (T(2) * ny * (x2 * z2));
+    Gz = g66 * (T(2) * nz * (x2 * y2));
     return;
   }
   a = T(1);

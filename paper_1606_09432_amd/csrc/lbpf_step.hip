@@ -63,7 +63,7 @@ template <class E> __device__ __forceinline__ void stb(E *base, unsigned boff, E
 
 // Minimum waves per SIMD the register allocator must leave room for.
 template <int DIM, int TY, class ST> constexpr int min_waves() {
-  return DIM == 2 ? (std::is_same<ST, StF64>::value ? 3 : 4) : (std::is_same<ST, StF64>::value ? 2 : (TY == 8 ? 4 : 3));
+  return DIM == 2 ? (std::is_same<ST, StF64>::value ? 3 : 5) : (std::is_same<ST, StF64>::value ? 2 : (TY == 8 ? 4 : 3));
 }
 
 // BATCH = false: one simulation (sd_arg); the work-group id gives the tile and

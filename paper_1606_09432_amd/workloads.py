@@ -29,7 +29,7 @@ LATTICES = ("D2Q9_D2Q5", "D3Q19_D3Q7", "D3Q15_D3Q7")
 BOUNDARIES = ("periodic", "zero_flux")
 GRADIENTS = ("dd", "cd")
 STORAGES = ("fp64", "fp32", "fp16")
-ANISO_KINDS = ("iso", "sectoral", "cubic", "cubic_hak")
+ANISO_KINDS = ("iso", "sectoral", "cubic", "cubic_hak", "cubic_s")
 
 
 @dataclass
@@ -39,6 +39,7 @@ class Aniso:
     kind ``sectoral``: 1 + eps Re[((n_x + i n_y) e^{-i phi0})^q] (Eq. As_Theta,
     Eq. As_Multi; Eq. As_Y66 in 3D with q = 6).  ``cubic``: Eq.
     As_Function_Classical.  ``cubic_hak``: Eq. As_MatSci with (eps, gamma).
+    ``cubic_s``: Eq. As_Function_S, 1 + 66 gamma n_x^2 n_y^2 n_z^2.
     """
 
     kind: str = "iso"
@@ -228,6 +229,27 @@ def e2(gradient: str = "dd", n: int = 800, storage: str = "fp64") -> SimConfig:
 
 
 E2_STEPS = 100000
+
+
+# The paper's 3D runs of Sec. 5 (D3Q15 + D3Q7, 351^3, seed at the centre):
+# dendrite A Eq. As_Function_Classical eps = 0.05, dendrite B Eq. As_MatSci
+# eps = 0, gamma = -0.02, dendrite C Eq. As_Function_S gamma = 0.02; with the
+# step counts read from the caption of the dendrite figure and the wall-clock
+# times the paper gives for 100 CPU cores.
+PAPER3D = {
+    "A": (Aniso("cubic", eps=0.05), 5000, 3.0 * 3600),
+    "B": (Aniso("cubic_hak", eps=0.0, gamma=-0.02), 25000, 8.97 * 3600),
+    "C": (Aniso("cubic_s", gamma=0.02), 15000, 9.18 * 3600),
+}
+
+
+def paper3d(dendrite: str = "A", storage: str = "fp64", n: int = 351) -> SimConfig:
+    entry = PAPER3D[dendrite][0]
+    c = n // 2
+    return SimConfig(
+        lattice="D3Q15_D3Q7", nx=n, ny=n, nz=n, boundary="zero_flux", gradient="dd", storage=storage,
+        W0=0.0125, tau0=1.5625e-4, lam=10.0, kappa=1.0, delta=0.3, dx=0.01, dt=1.5e-5, aniso=[entry],
+        seeds=[Seed(c, c, c, 10.0, 1)], tip_dir=(1, 0, 0))
 
 
 def multi_3d(storage: str = "fp64", lattice: str = "D3Q19_D3Q7", gradient: str = "dd",

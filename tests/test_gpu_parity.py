@@ -107,6 +107,7 @@ def test_2d_distributions_parity(gpu, oracle_mod):
     ("zero_flux", "cd", (66, 20, 18), W.Aniso("cubic_hak", eps=0.1, gamma=0.0), 40),
     ("zero_flux", "dd", (3, 3, 3), W.Aniso("cubic", eps=0.05), 10),
     ("periodic", "dd", (24, 24, 24), W.Aniso("sectoral", eps=0.05, q=6, phi0=0.0), 40),
+    ("zero_flux", "dd", (36, 34, 40), W.Aniso("cubic_s", gamma=0.02), 60),
 ])
 def test_3d_fp64_parity(gpu, oracle_mod, boundary, grad, shape, entry, steps):
     nx, ny, nz = shape

@@ -203,7 +203,8 @@ def test_dd_closed_form_d3q15(oracle_mod):
 # P4: anisotropy and flux N (Sec. 2 Eq. TermesAnisotropes, Sec. 4.1).
 # ---------------------------------------------------------------------------
 ENTRIES_3D = [W.Aniso("cubic", eps=0.05), W.Aniso("cubic_hak", eps=0.1, gamma=-0.02),
-              W.Aniso("cubic_hak", eps=0.0, gamma=-0.05), W.Aniso("sectoral", eps=0.05, q=6, phi0=0.2)]
+              W.Aniso("cubic_hak", eps=0.0, gamma=-0.05), W.Aniso("sectoral", eps=0.05, q=6, phi0=0.2),
+              W.Aniso("cubic_s", gamma=0.02)]
 ENTRIES_2D = [W.Aniso("sectoral", eps=0.05, q=q, phi0=t) for q, t in [(4, 0.0), (4, 0.35), (5, 1.1), (6, 0.0)]]
 
 
@@ -295,6 +296,15 @@ def test_cubic_harmonic_growth_directions(oracle_mod):
         for key, Q, S in [("100", 1.0, 0.0), ("110", 0.5, 0.0), ("111", 1 / 3, 1 / 27)]:
             expect = 1 + e1 * (Q - 0.6) + e2 * (3 * Q + 66 * S - 17 / 7)
             assert abs(vals[key] - expect) < 1e-14
+
+
+def test_s_form_favours_111(oracle_mod):
+    """Eq. As_Function_S (gamma = 0.02, Sec. 5) favours <111>: S = 0 on <100>
+    and <110>, 1/27 on <111>, so a = 1, 1, 1 + 66 gamma / 27."""
+    best, vals = _argmax_dir(oracle_mod, W.Aniso("cubic_s", gamma=0.02))
+    assert best == "111"
+    assert vals["100"] == 1.0 and vals["110"] == 1.0
+    assert abs(vals["111"] - (1 + 66 * 0.02 / 27)) < 1e-14
 
 
 # ---------------------------------------------------------------------------
