@@ -215,6 +215,86 @@ def profile_l2_error(phi, centre, n_a=(1.0, 0.0), n_b=(0.5, -math.sqrt(3.0) / 2.
     return float(np.sqrt(np.sum((pa - pb) ** 2) / np.sum(pa ** 2)))
 
 
+def _cubic_sample(phi, x, y):
+    """phi (indexed [y][x]) at the points (x, y) by cubic convolution (Keys, a = -1/2)."""
+    import numpy as np
+
+    x0 = np.floor(x).astype(int)
+    y0 = np.floor(y).astype(int)
+
+    def w(t):
+        t2, t3 = t * t, t * t * t
+        return [(-t3 + 2 * t2 - t) / 2, (3 * t3 - 5 * t2 + 2) / 2, (-3 * t3 + 4 * t2 + t) / 2, (t3 - t2) / 2]
+
+    wx, wy = w(x - x0), w(y - y0)
+    out = np.zeros_like(x, dtype=np.float64)
+    for a in range(4):
+        for b in range(4):
+            out += wy[a] * wx[b] * phi[y0 + a - 1, x0 + b - 1]
+    return out
+
+
+def tip_radius(phi, cx, cy, theta, rmax=40.0, dr=0.125):
+    """Distance from (cx, cy) to the phi = 0 crossing along the ray of angle
+    theta (the first sign change from solid to liquid, linearly interpolated)."""
+    import numpy as np
+
+    r = np.arange(0.0, rmax, dr)
+    v = _cubic_sample(phi, cx + r * math.cos(theta), cy + r * math.sin(theta))
+    k = np.nonzero((v[:-1] > 0) & (v[1:] <= 0))[0]
+    if len(k) == 0:
+        return float("nan")
+    i = int(k[0])
+    return float(r[i] + dr * v[i] / (v[i] - v[i + 1]))
+
+
+def run_orientation_spread(storage: str, n_orient: int = 10, side: int = 400, stop_radius: float = 80.0,
+                           max_steps: int = 40000):
+    """Orientation dependence of the growth with directional derivatives and with
+    central differences.  One batched ensemble holds, for each gradient method,
+    n_orient independent simulations of the twenty-crystal workload's physics
+    (four-fold a_s, eps = 0.05, Delta = 0.5, zero-flux side^2 boxes with a
+    centred seed of radius 5) whose crystal orientation theta0 runs over
+    [0, pi/4].  When the largest tip is stop_radius from the centre, the tip
+    radius along theta0 is compared across orientations: with an isotropic
+    discretisation it would not depend on theta0."""
+    import numpy as np
+
+    import paper_1606_09432_amd as lb
+    from paper_1606_09432_amd import workloads as W
+
+    thetas = [k * (math.pi / 4) / (n_orient - 1) for k in range(n_orient)]
+    c = side / 2.0
+    cfgs = []
+    for grad in ("dd", "cd"):
+        for t in thetas:
+            cfgs.append(W.SimConfig(lattice="D2Q9_D2Q5", nx=side, ny=side, nz=1, boundary="zero_flux",
+                                    gradient=grad, storage=storage, delta=0.5, kappa=W.KAPPA_C0,
+                                    aniso=[W.Aniso("sectoral", eps=0.05, q=4, phi0=t)],
+                                    seeds=[W.Seed(c, c, 0.0, 5.0, 1)], tip_dir=(1, 0, 0)))
+    sim = lb.Simulation(cfgs)
+    done = 0
+    radii = None
+    while done < max_steps:
+        sim.step(500)
+        done += 500
+        radii = [tip_radius(sim.fields(k)[0].cpu().numpy(), c, c, thetas[k % n_orient], rmax=side / 2 - 4)
+                 for k in range(len(cfgs))]
+        print(f"[orientation] step {done}: largest tip radius {max(radii):.2f}", file=sys.stderr, flush=True)
+        if max(radii) >= stop_radius:
+            break
+    sim.close()
+    out = {"workload": f"{n_orient} orientations x (DD, CD), {side}^2 each, four-fold a_s eps 0.05, Delta 0.5",
+           "steps": done, "storage": storage, "theta0": [round(t, 4) for t in thetas]}
+    for j, name in enumerate(("dd", "cd")):
+        r = np.array(radii[j * n_orient:(j + 1) * n_orient])
+        out[f"tip_radius_{name}"] = [round(float(v), 3) for v in r]
+        out[f"cv_{name}"] = float(r.std() / r.mean())
+        out[f"spread_{name}"] = float(r.max() - r.min())
+    out["cv_cd_over_dd"] = out["cv_cd"] / out["cv_dd"]
+    return out
+
+
 def run_isotropy(steps: int, storage: str):
     """The isotropy comparison of Sec. 4.2 (six-fold a_s, 800^2): the DD and CD
     runs advance together as one batched ensemble; prints Err_l2 of each and
@@ -398,6 +478,8 @@ def main():
                     help="only report the FP32/FP16-offset error against FP64 over a run")
     ap.add_argument("--paper3d", action="store_true",
                     help="only time the paper's 351^3 D3Q15 runs (context for its wall-clock times)")
+    ap.add_argument("--orientation", action="store_true",
+                    help="only run the DD/CD orientation-dependence measurement (four-fold crystals)")
     ap.add_argument("--isotropy", type=int, default=0, metavar="STEPS",
                     help="only run the six-fold DD/CD isotropy comparison for STEPS steps")
     ap.add_argument("--acc-steps", type=int, default=2000)
@@ -424,6 +506,9 @@ def main():
     if args.paper3d:
         for row in run_paper3d(args.steps, args.warmup):
             print(json.dumps(row), flush=True)
+        return
+    if args.orientation:
+        print(json.dumps(run_orientation_spread(args.only or "fp64")), flush=True)
         return
     if args.isotropy:
         print(json.dumps(run_isotropy(args.isotropy, args.only or "fp64")), flush=True)

@@ -39,3 +39,15 @@ def test_l2_metric_small_for_sixfold_symmetric_fronts(harmonic):
 
 def test_l2_metric_detects_threefold_front():
     assert bench.profile_l2_error(_front(harmonic=3), (400, 400)) > 0.1
+
+
+def test_tip_radius_on_fourfold_front():
+    # a four-fold front r = 15 (1 + 0.1 cos 4 (theta - 0.3)) around an off-node centre
+    n = 200
+    y, x = np.mgrid[0:n, 0:n].astype(float)
+    cx, cy = 100.3, 99.6
+    r = np.hypot(x - cx, y - cy)
+    th = np.arctan2(y - cy, x - cx)
+    phi = np.tanh((15 * (1 + 0.1 * np.cos(4 * (th - 0.3))) - r) / 2.5)
+    for t in (0.3, 0.3 + math.pi / 2, 0.3 + math.pi / 4):
+        assert abs(bench.tip_radius(phi, cx, cy, t) - 15 * (1 + 0.1 * math.cos(4 * (t - 0.3)))) < 0.01
