@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbpf.so")
 SOURCES = ["lbpf_step.hip", "lbpf_aux.hip", "lbpf_api.hip"]
-ARCH = os.environ.get("LBPF_OFFLOAD_ARCH", "gfx950")
+ARCH = "gfx950"  # MI355X
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
