@@ -330,10 +330,13 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
           p1 = (phiS[rs(pm + 1)][pc] - phiS[rs(pm - 1)][pc]) / T(2);
         }
       } else {
+        // e_i and -e_i give the same term w_i e_i (e_i . grad phi): one of each
+        // pair, with the central difference phi(x + e_i) - phi(x - e_i)
   #pragma unroll
         for (int i = 1; i < QP; ++i) {
+          if (LP::OPP[i] < i) continue;
           const int o = ey<LP, DIM>(i) * PX + ex<LP, DIM>(i);
-          const T dd = (phiS[rs(pm + em<LP, DIM>(i))][pc + o] - phiS[rs(pm - em<LP, DIM>(i))][pc - o]) / T(2);
+          const T dd = phiS[rs(pm + em<LP, DIM>(i))][pc + o] - phiS[rs(pm - em<LP, DIM>(i))][pc - o];
           if (LP::E[i][0] != 0) p0 += (T(LP::W[i]) * T(LP::E[i][0])) * dd;
           if (LP::E[i][1] != 0) p1 += (T(LP::W[i]) * T(LP::E[i][1])) * dd;
           if (LP::E[i][2] != 0) p2 += (T(LP::W[i]) * T(LP::E[i][2])) * dd;
