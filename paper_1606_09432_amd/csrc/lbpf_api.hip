@@ -28,6 +28,7 @@ int fail(int code, const std::string &msg) {
   } while (0)
 
 constexpr size_t kAlign = 256;
+constexpr long long kFieldSkew = 17 * 64;  // elements
 size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
 
 struct SimHost {
@@ -192,7 +193,11 @@ void plan(const lbpf_config &c, SimHost &s, size_t &cursor) {
   s.nm = s.dim == 3 ? c.nz : c.ny;
   s.pitch = (int)align_up((size_t)c.nx, 64);
   s.mstride = (long long)s.pitch * s.nyp;
-  s.fstride = s.mstride * s.nm;
+  // Consecutive direction fields are offset by 17 x 64 extra elements: with a
+  // power-of-two field size (512^3) the same node of every direction would
+  // otherwise sit at the same address modulo large powers of two, i.e. in the
+  // same HBM channel for all 26 concurrent streams.
+  s.fstride = s.mstride * s.nm + kFieldSkew;
   s.dsz = c.storage == LBPF_FP64 ? 8 : (c.storage == LBPF_FP32_OFFSET ? 4 : 2);
   s.psz = c.storage == LBPF_FP64 ? 8 : 4;
   const size_t field = (size_t)s.fstride;
