@@ -35,6 +35,14 @@
  *     takes the post-collision g_i'* of the same node (no nonlocal term).  The
  *     same rule holds for f.  Ghost phi values for gradients are mirrored about
  *     the wall node: phi(-1) = phi(1).
+ *   - Symmetric boxes (mirror_low): Sec. 5 computes one octant of a dendrite
+ *     grown from a seed at the origin and completes it by symmetry about the
+ *     planes XY, YZ and XZ, without saying how the symmetry planes are
+ *     treated.  Here they are exact mirror planes through node 0: the state
+ *     beyond them is the mirror image of the state inside (phi, u and the
+ *     index at -k are those at +k; the population i there is the mirror image
+ *     of population i' at +k), and each pass applies its own rule to that
+ *     mirror-extended state.  The far walls are zero flux.
  *   - |p| <= 1e-8 (lattice units): n is taken as undefined, a_s = 1, N = 0.
  *     The paper leaves n = -grad phi/|grad phi| undefined where the gradient
  *     vanishes.  Below 1e-8 the FP64 rounding of the phi differences (about
@@ -338,6 +346,7 @@ static int inside(int c, int n, int periodic) {
   return (c < 0 || c >= n) ? -1 : c;
 }
 
+/* Node x + sign e as the push sees it: no mirror images (-1 if outside). */
 static long partner(const orc_sim *S, int x, int y, int z, const int *e, int sign) {
   const int per = S->cfg.periodic;
   const int X = inside(x + sign * e[0], S->nx, per);
@@ -345,6 +354,37 @@ static long partner(const orc_sim *S, int x, int y, int z, const int *e, int sig
   const int Z = inside(z + sign * e[2], S->nz, per);
   if (X < 0 || Y < 0 || Z < 0) return -1;
   return nid(S, X, Y, Z);
+}
+
+/* Node x + sign e with the mirror planes of a symmetric box (mirror_low): the
+ * planes through node 0 of every axis are planes of mirror symmetry of the
+ * whole domain (the box is one octant of it, one quadrant in 2D; Sec. 5 runs a
+ * dendrite this way), so a coordinate -k stands for the node at +k.  Bit k of
+ * *flip is set when axis k was mirrored.  -1 beyond a zero-flux wall. */
+static long partner_sym(const orc_sim *S, int x, int y, int z, const int *e, int sign, int *flip) {
+  const int n[3] = {S->nx, S->ny, S->nz};
+  int c[3] = {x + sign * e[0], y + sign * e[1], z + sign * e[2]};
+  *flip = 0;
+  for (int k = 0; k < 3; ++k) {
+    if (S->cfg.mirror_low && c[k] < 0) {
+      c[k] = -c[k];
+      *flip |= 1 << k;
+    }
+  }
+  if (*flip == 0) return partner(S, x, y, z, e, sign);
+  for (int k = 0; k < 3; ++k)
+    if (c[k] >= n[k]) return -1;
+  return nid(S, c[0], c[1], c[2]);
+}
+
+/* Direction of lattice L whose vector is e_i with the components of the axes
+ * in flip negated: the mirror image of direction i. */
+static int mirror_dir(const lat_t *L, int i, int flip) {
+  int t[3];
+  for (int k = 0; k < 3; ++k) t[k] = (flip >> k & 1) ? -L->e[i][k] : L->e[i][k];
+  for (int j = 0; j < L->q; ++j)
+    if (L->e[j][0] == t[0] && L->e[j][1] == t[1] && L->e[j][2] == t[2]) return j;
+  return -1;
 }
 
 static const orc_aniso *entry_for(const orc_sim *S, int id) {
@@ -418,7 +458,8 @@ static void pass_ids(orc_sim *S) {
         double best = -HUGE_VAL;
         int16_t bid = 0;
         for (int i = 1; i < L->q; ++i) {
-          const long m = partner(S, x, y, z, L->e[i], +1);
+          int fl;
+          const long m = partner_sym(S, x, y, z, L->e[i], +1, &fl);
           if (m < 0 || S->id[m] == 0) continue;
           const double ph = S->phi[m];
           if (ph > best || (ph == best && S->id[m] < bid)) {
@@ -493,7 +534,37 @@ static void pass_phi_lbe(orc_sim *S) {
   }
 }
 
-/* Pass 5: bounce-back of Eq. Bounce-Back on the unknown incoming g. */
+/* Pass 4b (mirror_low only): g_i arriving at y from a source x = y - e_i
+ * beyond a mirror plane.  In the symmetric domain that source holds the mirror
+ * image of the node x' inside, with direction i' the mirror image of i, so the
+ * update of Eq. LBE_Eq_Phase takes g_i'(x'), g^(0)_i'(x'), eta, Q and a_s^2 at
+ * x' (w_i' = w_i). */
+static void pass_phi_mirror(orc_sim *S) {
+  if (!S->cfg.mirror_low) return;
+  const lat_t *L = &S->lp;
+  const long N = S->N;
+#pragma omp parallel for schedule(static)
+  for (long row = 0; row < (long)S->nz * S->ny; ++row) {
+    const int z = (int)(row / S->ny), y = (int)(row % S->ny);
+    for (int x = 0; x < S->nx; ++x) {
+      const long d = nid(S, x, y, z);
+      for (int i = 1; i < L->q; ++i) {
+        int fl;
+        const long c = partner_sym(S, x, y, z, L->e[i], -1, &fl);
+        if (c < 0 || fl == 0) continue;
+        const int j = mirror_dir(L, i, fl);
+        const double a2 = S->a[c] * S->a[c];
+        const double gx = S->g[(long)j * N + c];
+        const double gy = S->g[(long)i * N + d];
+        const double rhs = gx - (1.0 - a2) * gy - (gx - geq(S, j, c)) / S->eta[c] + L->w[j] * S->Q[c] * S->s;
+        S->gn[(long)i * N + d] = rhs / a2;
+      }
+    }
+  }
+}
+
+/* Pass 5: bounce-back of Eq. Bounce-Back on the unknown incoming g (sources
+ * beyond a zero-flux wall). */
 static void pass_phi_bounce(orc_sim *S) {
   if (S->cfg.periodic) return;
   const lat_t *L = &S->lp;
@@ -504,9 +575,10 @@ static void pass_phi_bounce(orc_sim *S) {
     for (int x = 0; x < S->nx; ++x) {
       const long c = nid(S, x, y, z);
       for (int i = 1; i < L->q; ++i) {
-        if (partner(S, x, y, z, L->e[i], -1) >= 0) continue; /* streamed in */
+        int fl;
+        if (partner_sym(S, x, y, z, L->e[i], -1, &fl) >= 0) continue; /* streamed in or mirrored */
         const int j = L->opp[i];
-        if (partner(S, x, y, z, L->e[j], -1) >= 0)
+        if (partner_sym(S, x, y, z, L->e[j], -1, &fl) >= 0)
           S->gn[(long)i * N + c] = S->gn[(long)j * N + c];
         else
           S->gn[(long)i * N + c] = gstar_local(S, j, c);
@@ -548,6 +620,22 @@ static void pass_heat(orc_sim *S) {
       }
     }
   }
+  if (S->cfg.mirror_low) {
+    /* f_i arriving from beyond a mirror plane: the mirror image i' of i,
+     * collided at the mirror node x' inside */
+#pragma omp parallel for schedule(static)
+    for (long row = 0; row < (long)S->nz * S->ny; ++row) {
+      const int z = (int)(row / S->ny), y = (int)(row % S->ny);
+      for (int x = 0; x < S->nx; ++x) {
+        const long d = nid(S, x, y, z);
+        for (int i = 1; i < L->q; ++i) {
+          int fl;
+          const long c = partner_sym(S, x, y, z, L->e[i], -1, &fl);
+          if (c >= 0 && fl != 0) S->fn[(long)i * N + d] = fstar(S, mirror_dir(L, i, fl), c);
+        }
+      }
+    }
+  }
   if (!S->cfg.periodic) {
 #pragma omp parallel for schedule(static)
     for (long row = 0; row < (long)S->nz * S->ny; ++row) {
@@ -555,9 +643,10 @@ static void pass_heat(orc_sim *S) {
       for (int x = 0; x < S->nx; ++x) {
         const long c = nid(S, x, y, z);
         for (int i = 1; i < L->q; ++i) {
-          if (partner(S, x, y, z, L->e[i], -1) >= 0) continue;
+          int fl;
+          if (partner_sym(S, x, y, z, L->e[i], -1, &fl) >= 0) continue;
           const int j = L->opp[i];
-          if (partner(S, x, y, z, L->e[j], -1) >= 0)
+          if (partner_sym(S, x, y, z, L->e[j], -1, &fl) >= 0)
             S->fn[(long)i * N + c] = S->fn[(long)j * N + c];
           else
             S->fn[(long)i * N + c] = fstar(S, j, c);
@@ -587,6 +676,7 @@ int orc_step(orc_sim *S, int nsteps) {
     if (S->cfg.use_ids) pass_ids(S);
     pass_params(S);
     pass_phi_lbe(S);
+    pass_phi_mirror(S);
     pass_phi_bounce(S);
     pass_phi_moment(S);
     pass_heat(S);
@@ -647,6 +737,7 @@ int orc_create(const orc_config *cfg, orc_sim **out) {
     if (kd == ORC_ANISO_SECTORAL && cfg->aniso[k].q < 1) return -1;
   }
   if (cfg->use_ids && cfg->aniso[0].kind != ORC_ANISO_ISO) return -1;
+  if (cfg->mirror_low && cfg->periodic) return -1;
   for (int k = 0; k < cfg->n_seeds; ++k)
     if (cfg->seeds[k].id < 0 || (cfg->use_ids && cfg->seeds[k].id >= cfg->n_aniso)) return -1;
 

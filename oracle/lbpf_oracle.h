@@ -59,6 +59,8 @@ typedef struct {
   const orc_seed *seeds;
   int32_t tip_dir[3];   /* integer lattice direction of the tip ray from seed 0's centre */
   int32_t q_phi;        /* phi lattice: 0 default (D2Q9 / D3Q19), or 15 for D3Q15 in 3D */
+  int32_t mirror_low;   /* 1: the planes through node 0 of every axis are mirror planes of a
+                           symmetric domain (periodic must be 0); the far walls stay zero flux */
 } orc_config;
 
 typedef struct orc_sim orc_sim;

@@ -36,7 +36,7 @@ class OrcConfig(C.Structure):
                 ("dt", C.c_double), ("xi", C.c_double),
                 ("n_aniso", C.c_int32), ("aniso", C.POINTER(OrcAniso)),
                 ("n_seeds", C.c_int32), ("seeds", C.POINTER(OrcSeed)),
-                ("tip_dir", C.c_int32 * 3), ("q_phi", C.c_int32)]
+                ("tip_dir", C.c_int32 * 3), ("q_phi", C.c_int32), ("mirror_low", C.c_int32)]
 
 
 class OrcDiag(C.Structure):
@@ -111,6 +111,7 @@ class OracleSim:
         c.q_phi = 15 if cfg.lattice == "D3Q15_D3Q7" else 0
         c.nx, c.ny, c.nz = cfg.nx, cfg.ny, cfg.nz
         c.periodic = 1 if cfg.boundary == "periodic" else 0
+        c.mirror_low = 1 if cfg.boundary == "mirror_low" else 0
         c.grad_cd = 1 if cfg.gradient == "cd" else 0
         c.use_ids = 1 if cfg.use_ids else 0
         c.W0, c.tau0, c.lam, c.kappa = cfg.W0, cfg.tau0, cfg.lam, cfg.kappa

@@ -569,6 +569,72 @@ def test_mirror_symmetry_with_walls(oracle_mod):
     assert np.array_equal(phi, phi[:, ::-1]) and np.array_equal(phi, phi[::-1, :])
 
 
+def _octant_pair(lattice, n, grad="dd", ids=False):
+    """A symmetric zero-flux domain of 2n - 1 nodes per axis with the centre
+    node c = n - 1, and its octant (quadrant in 2D): n nodes per axis whose
+    planes through node 0 are the symmetry planes (Sec. 5, dendrite B)."""
+    dim = 2 if lattice == "D2Q9_D2Q5" else 3
+    N = 2 * n - 1
+    c = n - 1
+    if dim == 2:
+        entry = W.Aniso("sectoral", eps=0.05, q=4, phi0=0.0)
+        # one seed on the centre and one off the planes, with its mirror images
+        base = [(0.0, 0.0, 0.0, 4.0, 1), (9.0, 5.0, 0.0, 3.0, 2 if ids else 1)]
+    else:
+        entry = W.Aniso("cubic_hak", eps=0.04, gamma=-0.02)
+        base = [(0.0, 0.0, 0.0, 4.0, 1), (7.0, 3.0, 5.0, 2.5, 2 if ids else 1)]
+    full_seeds, oct_seeds = [], []
+    for (x, y, z, r, k) in base:
+        oct_seeds.append(W.Seed(x, y, z, r, k))
+        for sx in {x, -x}:
+            for sy in {y, -y}:
+                for sz in ({z, -z} if dim == 3 else {0.0}):
+                    full_seeds.append(W.Seed(c + sx, c + sy, (c + sz) if dim == 3 else 0.0, r, k))
+    aniso = [W.Aniso("iso"), entry, entry] if ids else [entry]
+    full = W.SimConfig(lattice=lattice, nx=N, ny=N, nz=N if dim == 3 else 1, boundary="zero_flux",
+                       gradient=grad, storage="fp64", delta=0.55, kappa=W.KAPPA_C0, aniso=aniso,
+                       seeds=full_seeds, use_ids=ids, tip_dir=(1, 0, 0))
+    octant = full.replace(nx=n, ny=n, nz=n if dim == 3 else 1, boundary="mirror_low", seeds=oct_seeds)
+    return full, octant, c, dim
+
+
+@pytest.mark.parametrize("lattice,n,grad,ids", [
+    ("D2Q9_D2Q5", 26, "dd", False), ("D2Q9_D2Q5", 26, "cd", True),
+    ("D3Q19_D3Q7", 13, "dd", True), ("D3Q15_D3Q7", 13, "dd", False), ("D3Q19_D3Q7", 13, "cd", False)])
+def test_mirror_box_is_one_octant_of_the_symmetric_domain(oracle_mod, lattice, n, grad, ids):
+    """A box with mirror planes through node 0 advances exactly as one octant
+    of the mirror-symmetric zero-flux domain: the symmetry planes are the only
+    difference, and every rule for them (mirrored sources and directions for g
+    and f, the parameters at the mirror node, index neighbours) shows here."""
+    full_cfg, oct_cfg, c, dim = _octant_pair(lattice, n, grad, ids)
+    full = oracle_mod.OracleSim(full_cfg)
+    octant = oracle_mod.OracleSim(oct_cfg)
+    part = (slice(c, None),) * dim
+    for _ in range(3):
+        full.step(60)
+        octant.step(60)
+        assert np.abs(octant.phi() - full.phi()[part]).max() <= 1e-13
+        assert np.abs(octant.u() - full.u()[part]).max() <= 1e-13
+        if ids:
+            assert np.array_equal(octant.ids(), full.ids()[part])
+    # the populations too, each against the same direction of the full domain
+    assert np.abs(octant.g() - full.g()[(slice(None),) + part]).max() <= 1e-13
+    assert np.abs(octant.f() - full.f()[(slice(None),) + part]).max() <= 1e-13
+    # the crystal has grown across the symmetry planes' neighbourhood
+    assert (octant.phi()[(slice(0, 3),) * dim] > 0).all()
+
+
+def test_mirror_box_differs_from_walls(oracle_mod):
+    """The same octant with zero-flux walls instead of mirror planes gives a
+    different state, so the mirror pass is not a no-op."""
+    _, oct_cfg, _, _ = _octant_pair("D2Q9_D2Q5", 26)
+    a = oracle_mod.OracleSim(oct_cfg)
+    b = oracle_mod.OracleSim(oct_cfg.replace(boundary="zero_flux"))
+    a.step(60)
+    b.step(60)
+    assert np.abs(a.phi() - b.phi()).max() > 1e-3
+
+
 # ---------------------------------------------------------------------------
 # P14: determinism — serial and threaded oracle runs are bitwise equal.
 # ---------------------------------------------------------------------------
