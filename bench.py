@@ -33,7 +33,7 @@ HBM_PEAK_GBS = 8000.0
 B_ALG = {("D3Q19_D3Q7", "fp64"): 416, ("D3Q19_D3Q7", "fp32"): 224, ("D3Q19_D3Q7", "fp16"): 120,
          ("D3Q15_D3Q7", "fp64"): 352, ("D3Q15_D3Q7", "fp32"): 192, ("D3Q15_D3Q7", "fp16"): 104,
          ("D2Q9_D2Q5", "fp64"): 224, ("D2Q9_D2Q5", "fp32"): 128, ("D2Q9_D2Q5", "fp16"): 72}
-KERNEL_SOURCES = ["paper_1606_09432_amd/csrc/lbpf_step.hip", "paper_1606_09432_amd/csrc/lbpf_common.hpp"]
+KERNEL_SOURCES = ["paper_1606_09432_amd/csrc/lbpf_step_kernel.hpp", "paper_1606_09432_amd/csrc/lbpf_common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
 
 
@@ -345,6 +345,15 @@ def run_paper3d(steps: int, warmup: int):
                         "paper_steps": paper_steps, "time_for_paper_steps_s": r["ms_per_step"] * paper_steps / 1e3,
                         "paper_wall_clock_s": paper_seconds, "paper_hardware": "100 CPU cores (unnamed cluster)",
                         "paper_MLUPS": cfg.nodes * paper_steps / paper_seconds / 1e6})
+    # dendrite B grown from the origin of a box with mirror planes (one octant)
+    entry, paper_steps, paper_seconds, cores = W.PAPER3D_OCTANT
+    for st in ("fp64", "fp16"):
+        cfg = W.paper3d_octant(st)
+        r = run_gpu(cfg, steps, warmup, False)
+        out.append({"dendrite": "B, octant", "storage": st, "MLUPS": r["value"], "ms_per_step": r["ms_per_step"],
+                    "paper_steps": paper_steps, "time_for_paper_steps_s": r["ms_per_step"] * paper_steps / 1e3,
+                    "paper_wall_clock_s": paper_seconds, "paper_hardware": f"{cores} CPU cores (unnamed cluster)",
+                    "paper_MLUPS": cfg.nodes * paper_steps / paper_seconds / 1e6})
     return out
 
 

@@ -64,9 +64,19 @@ extern "C" {
 #define LBPF_D2Q9_D2Q5 0
 #define LBPF_D3Q19_D3Q7 1
 #define LBPF_D3Q15_D3Q7 2
-/* Boundaries: periodic box, or zero flux on every wall (Sec. 2, Eq. Bounce-Back). */
+/* Boundaries: periodic box, or zero flux on every wall (Sec. 2, Eq. Bounce-Back).
+ * LBPF_MIRROR_LOW: the box is one octant (one quadrant in 2D) of a domain that
+ * is mirror-symmetric about the planes through node 0 of each axis, as in the
+ * paper's 3D run with the seed at the origin, completed by symmetry about the
+ * planes XY, YZ and XZ (Sec. 5).  The state beyond those planes is the mirror
+ * image of the state inside (phi, u, the index and, for population i, the
+ * population of the mirrored direction at the mirror node); the far walls are
+ * zero flux.  Seeds belong at the origin or are mirrored with it; the
+ * anisotropy must be symmetric about the planes for the octant to stand for
+ * the whole domain. */
 #define LBPF_PERIODIC 0
 #define LBPF_ZERO_FLUX 1
+#define LBPF_MIRROR_LOW 2
 /* Gradient of phi: directional derivatives (Eq. Grad_DF-Centree) or central differences. */
 #define LBPF_GRAD_DD 0
 #define LBPF_GRAD_CD 1
@@ -101,7 +111,7 @@ typedef struct {
 typedef struct {
   int32_t lattice;   /* LBPF_D2Q9_D2Q5, LBPF_D3Q19_D3Q7 or LBPF_D3Q15_D3Q7 */
   int32_t nx, ny, nz;/* nz = 1 in 2D; every used extent >= 3 */
-  int32_t boundary;  /* LBPF_PERIODIC or LBPF_ZERO_FLUX */
+  int32_t boundary;  /* LBPF_PERIODIC, LBPF_ZERO_FLUX or LBPF_MIRROR_LOW */
   int32_t gradient;  /* LBPF_GRAD_DD or LBPF_GRAD_CD */
   int32_t storage;   /* LBPF_FP64, LBPF_FP32_OFFSET or LBPF_FP16_OFFSET */
   int32_t use_ids;   /* 0: entry 0 of aniso everywhere; 1: crystal index field

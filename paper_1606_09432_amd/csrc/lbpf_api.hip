@@ -61,6 +61,7 @@ constexpr int kGraphSteps = 8;     // steps per long graph (even: the parity is 
 struct BatchState {
   bool on = false;
   bool ids = false;
+  bool mirror = false;                 // some member has mirror planes
   int storage = 0;
   int chunk = 8;                       // rows per work item (measured best for the 256-member ensemble)
   size_t off_sims = 0, off_items = 0;  // workspace offsets
@@ -98,7 +99,8 @@ int validate(const lbpf_config &c) {
     if (elems * esize >= (1LL << 32))
       return fail(LBPF_ERR_ARG, "grid too large: one field must stay below 4 GiB (32-bit byte offsets)");
   }
-  if (c.boundary != LBPF_PERIODIC && c.boundary != LBPF_ZERO_FLUX) return fail(LBPF_ERR_ARG, "unknown boundary");
+  if (c.boundary != LBPF_PERIODIC && c.boundary != LBPF_ZERO_FLUX && c.boundary != LBPF_MIRROR_LOW)
+    return fail(LBPF_ERR_ARG, "unknown boundary");
   if (c.gradient != LBPF_GRAD_DD && c.gradient != LBPF_GRAD_CD) return fail(LBPF_ERR_ARG, "unknown gradient");
   if (c.storage < LBPF_FP64 || c.storage > LBPF_FP16_OFFSET) return fail(LBPF_ERR_ARG, "unknown storage");
   if (!(c.W0 > 0) || !(c.tau0 > 0) || !(c.dx > 0) || !(c.kappa > 0) || !std::isfinite(c.lambda) ||
@@ -241,6 +243,7 @@ SimDev make_dev(const lbpf_handle *h, const SimHost &s, int in) {
   d.mstride = s.mstride;
   d.fstride = s.fstride;
   d.periodic = s.cfg.boundary == LBPF_PERIODIC;
+  d.mirror = s.cfg.boundary == LBPF_MIRROR_LOW;
   d.grad_cd = s.cfg.gradient == LBPF_GRAD_CD;
   d.use_ids = s.cfg.use_ids != 0;
   d.n_aniso = s.cfg.n_aniso;
@@ -307,6 +310,8 @@ void plan_batch(const std::vector<SimHost> &sims, BatchState &b, size_t &total) 
   if (sims.size() < 2) return;
   b.on = true;
   b.ids = sims[0].cfg.use_ids != 0;
+  b.mirror = false;
+  for (const SimHost &sh : sims) b.mirror = b.mirror || sh.cfg.boundary == LBPF_MIRROR_LOW;
   b.storage = sims[0].storage;
   long long items = 0;
   for (const SimHost &s : sims) items += (long long)((s.nx + 63) / 64) * ((s.nm + kMinBatchChunk - 1) / kMinBatchChunk);
@@ -428,7 +433,7 @@ int lb_pf_init(const lbpf_config *cfgs, int n_sims, void *dev_workspace, size_t 
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&b.n_cu, hipDeviceAttributeMultiprocessorCount, dev);
-    b.blocks_per_cu = batch_blocks_per_cu(b.storage, b.ids);
+    b.blocks_per_cu = batch_blocks_per_cu(b.storage, b.ids, b.mirror);
     if (e == hipSuccess && b.blocks_per_cu < 1) e = hipErrorInvalidDeviceFunction;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b.cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
@@ -481,7 +486,7 @@ int batch_graph(lbpf_handle *h, int p, int kind) {
   HIPCHK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int k = 0; k < steps && le == hipSuccess; ++k)
-    le = launch_batch(b.storage, b.ids, tab + ((p + k) & 1) * n, items, b.n_items, b.grid, b.cap);
+    le = launch_batch(b.storage, b.ids, b.mirror, tab + ((p + k) & 1) * n, items, b.n_items, b.grid, b.cap);
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(b.cap, &g);
   if (le != hipSuccess || ee != hipSuccess) {

@@ -106,6 +106,25 @@ template <class L, int DIM> __device__ __forceinline__ constexpr int em(int i) {
   return DIM == 3 ? L::E[i][2] : L::E[i][1];
 }
 
+// Mirror image of direction i: the direction whose vector is e_i with the
+// components along the axes in fl negated (bit 0: x, bit 1: yp, bit 2: m).
+template <class L, int DIM> __device__ __forceinline__ constexpr int mirror_dir(int i, int fl) {
+  const int tx = (fl & 1) ? -ex<L, DIM>(i) : ex<L, DIM>(i);
+  const int ty = (fl & 2) ? -ey<L, DIM>(i) : ey<L, DIM>(i);
+  const int tm = (fl & 4) ? -em<L, DIM>(i) : em<L, DIM>(i);
+  for (int j = 0; j < L::Q; ++j)
+    if (ex<L, DIM>(j) == tx && ey<L, DIM>(j) == ty && em<L, DIM>(j) == tm) return j;
+  return i;
+}
+// The same for a compile-time i and a runtime fl: a choice among eight constants.
+template <class L, int DIM> __device__ __forceinline__ int mirror_sel(int i, int fl) {
+  int r = i;
+#pragma unroll
+  for (int f = 1; f < 8; ++f)
+    if (fl == f) r = mirror_dir<L, DIM>(i, f);
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // Storage: FP64 distributions, or FP32 arithmetic on offsets stored in FP32/FP16.
 // ---------------------------------------------------------------------------
@@ -168,6 +187,7 @@ struct SimDev {
   const int16_t *id_in;
   int16_t *id_out;
   const AnisoDev *aniso;
+  int mirror;  // the planes through node 0 of each axis are mirror planes
 };
 
 __device__ __forceinline__ bool in_range(int c, int n) { return (unsigned)c < (unsigned)n; }
@@ -279,7 +299,10 @@ __device__ __forceinline__ void flux(const AnisoDev *A, T px, T py, T pz, T &a, 
 // Heat distributions are stored post-collision at their source node
 // ("stream on read"): f_i^n(y) = f*_i(y - e_i).  With zero-flux walls an
 // unknown f_i (source outside) is the opposite population f_i'^n(y) = f*_i'(y + e_i)
-// (Eq. Bounce-Back); if that source is outside too, f*_i'(y).
+// (Eq. Bounce-Back); if that source is outside too, f*_i'(y).  A source beyond
+// a mirror plane is the mirror node inside, and the population there is the
+// mirror image of i: the opposite one, since the heat lattices' vectors have
+// one nonzero component.
 // gather_u returns u^n(y) = sum_i f_i^n(y) and the decoded populations:
 //   FP64:     fd[i] = f_i^n(y)
 //   offsets:  fd[i] = f_i^n(y) - w_i u*(y), stored f*_i = w_i u* + k_i.
@@ -300,6 +323,12 @@ __device__ __forceinline__ typename ST::T gather_u(const SimDev &sd, int x, int 
     int sx = x - ex<LU, DIM>(i), sy = yp - ey<LU, DIM>(i), sm = m - em<LU, DIM>(i);
     int d = i;
     unsigned src;
+    if (sd.mirror && (sx < 0 || sy < 0 || sm < 0)) {
+      d = LU::OPP[i];
+      sx = abs(sx);
+      sy = abs(sy);
+      sm = abs(sm);
+    }
     if (sd.periodic) {
       src = lin(sd, wrapc(sx, sd.nx), DIM == 3 ? wrapc(sy, sd.nyp) : 0, wrapc(sm, sd.nm));
     } else if (in_range(sx, sd.nx) && (DIM == 2 || in_range(sy, sd.nyp)) && in_range(sm, sd.nm)) {

@@ -44,11 +44,17 @@ constexpr int kDiagBlocks = 512;
 
 // lattice: pair code (0 D2Q9/D2Q5, 1 D3Q19/D3Q7, 2 D3Q15/D3Q7).
 hipError_t launch_step(int lattice, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st);
-// sims: the SimDev of every simulation for the step's parity (device memory).
-hipError_t launch_batch(int storage, bool ids, const SimDev *sims, const BatchItem *items, int n_items, int grid,
-                        hipStream_t st);
+// sims: the SimDev of every simulation for the step's parity (device memory);
+// mirror: some simulation of the ensemble has mirror planes.
+hipError_t launch_batch(int storage, bool ids, bool mirror, const SimDev *sims, const BatchItem *items, int n_items,
+                        int grid, hipStream_t st);
 // Resident work-groups per compute unit of the batch kernel (0 on failure).
-int batch_blocks_per_cu(int storage, bool ids);
+int batch_blocks_per_cu(int storage, bool ids, bool mirror);
+// The instances with mirror planes (lbpf_step_mirror.hip).
+hipError_t launch_step_mirror(int lattice, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st);
+hipError_t launch_batch_mirror(int storage, bool ids, const SimDev *sims, const BatchItem *items, int n_items,
+                               int grid, hipStream_t st);
+int batch_blocks_per_cu_mirror(int storage, bool ids);
 hipError_t launch_init(int lattice, int storage, const SimDev &sd, int16_t *ids_out, const InitSrc &src,
                        hipStream_t st);
 hipError_t launch_diag(int dim, int storage, const SimDev &sd, double *partials, double *result,

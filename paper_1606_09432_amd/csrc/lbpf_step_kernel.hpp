@@ -37,6 +37,8 @@
 //   h*_i(x) = A h_i(x) + w_i (Q s + e_i . C),  A = 1 - w,  C = -w (Dphi/e^2) N
 //   d_i     = h_i(y) + [w_i (phi(x) - phi(y)) + h*_i(x) - h_i(y)] / a^2(x)
 //   phi^{n+1}(y) = phi^n(y) + sum_i d_i,   h_i^{n+1}(y) = d_i - w_i sum_j d_j.
+#pragma once
+
 #include <type_traits>
 
 #include "lbpf_kernels.hpp"
@@ -71,7 +73,11 @@ template <int DIM, int TY, class ST> constexpr int min_waves() {
 // list `items` of a batched ensemble, whose per-simulation state is sims[k];
 // items are in decreasing cost and work-group b takes items b, b + G, b + 2G,
 // ... (G = grid size): static balance, no atomics, no per-step reset.
-template <int K, int TY, class ST, bool IDS, bool BATCH>
+// MIR = true adds the mirror planes through node 0 (SimDev::mirror): a source
+// x = y - e_i beyond one is the mirror node x' inside, whose population is the
+// mirror image i' of i and whose coefficients give the update, with the
+// component of e . C taken along i'.
+template <int K, int TY, class ST, bool IDS, bool BATCH, bool MIR>
 __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(min_waves<LatOf<K>::DIM, TY, ST>(), 8))) void
 step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const BatchItem *__restrict__ items,
             int n_items) {
@@ -199,10 +205,21 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
     // heat population i pulled by node (gx, gy, gm): stored field d at node src,
     // which sits at ring offset (ox, oy, om) from the node.  Bounce-back for
     // sources outside the box (Eq. Bounce-Back): the opposite population pulled
-    // from y + e_i, or the node's own post-collision opposite population.
+    // from y + e_i, or the node's own post-collision opposite population.  A
+    // source beyond a mirror plane is the mirror node, population OPP[i] (one
+    // nonzero component); the ring holds the mirror values at offset -e_i.
     auto heat_src = [&](int gx, int gy, int gm, int i, unsigned &src, int &d, int &ox, int &oy, int &om) {
       const int cx = ex<LU, DIM>(i), cy = ey<LU, DIM>(i), cm = em<LU, DIM>(i);
       int sx = gx - cx, sy = gy - cy, sm = gm - cm;
+      bool flip = false;
+      if constexpr (MIR) {
+        if (sd.mirror) {
+          flip = (sx < 0) | (sy < 0) | (sm < 0);
+          sx = abs(sx);
+          sy = abs(sy);
+          sm = abs(sm);
+        }
+      }
       bool in1;
       if (per) {
         sx = wrapc(sx, sd.nx);
@@ -218,7 +235,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       const int ry = in1 ? sy : (in2 ? ty_ : gy);
       const int rm = in1 ? sm : (in2 ? tm_ : gm);
       src = lin(sd, rx, ry, rm);
-      d = in1 ? i : LU::OPP[i];
+      d = (in1 && !flip) ? i : LU::OPP[i];
       ox = in1 ? -cx : (in2 ? cx : 0);
       oy = in1 ? -cy : (in2 ? cy : 0);
       om = in1 ? -cm : (in2 ? cm : 0);
@@ -436,11 +453,13 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       const unsigned iyb = iy * (unsigned)sizeof(S);
       S gy_r[QP], gx_r[QP];
       bool unk[QP];
+      int flm[QP];  // mirrored axes of each source (bit 0 x, 1 yp, 2 m)
       // one batch of loads: g_i(y) and g_i(y - e_i)
       if (xy_in1 && m >= 1 && m + 1 < sd.nm) {
   #pragma unroll
         for (int i = 0; i < QP; ++i) {
           unk[i] = false;
+          flm[i] = 0;
           gy_r[i] = ldb(gfield(i), iyb);
           gx_r[i] = ldb(gfield(i), iyb + boff_of(ex<LP, DIM>(i), ey<LP, DIM>(i), em<LP, DIM>(i), sizeof(S)));
         }
@@ -449,6 +468,15 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
         for (int i = 0; i < QP; ++i) {
           const int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
           int sx = gx_o - cx, sy = gy_o - cy, sm = m - cm;
+          flm[i] = 0;
+          if constexpr (MIR) {
+            if (sd.mirror) {
+              flm[i] = (sx < 0 ? 1 : 0) | (sy < 0 ? 2 : 0) | (sm < 0 ? 4 : 0);
+              sx = abs(sx);
+              sy = abs(sy);
+              sm = abs(sm);
+            }
+          }
           if (per) {
             sx = wrapc(sx, sd.nx);
             sy = (DIM == 3) ? wrapc(sy, sd.nyp) : 0;
@@ -459,14 +487,25 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
           }
           const unsigned isrc = unk[i] ? iy : lin(sd, sx, sy, sm);
           gy_r[i] = ldb(gfield(i), iyb);
-          gx_r[i] = ldb(gfield(i), isrc * (unsigned)sizeof(S));
+          if constexpr (MIR) {
+            gx_r[i] = ldb(gfield(mirror_sel<LP, DIM>(i, flm[i])), isrc * (unsigned)sizeof(S));
+          } else {
+            gx_r[i] = ldb(gfield(i), isrc * (unsigned)sizeof(S));
+          }
         }
       }
       const T phy = phiS[rs(m)][pco];
       T d[QP];
   #pragma unroll
       for (int i = 0; i < QP; ++i) {
-        const int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
+        int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
+        T sgn0 = T(1), sgn1 = T(1), sgn2 = T(1);
+        if constexpr (MIR) {
+          // a mirrored source sits at y + e_i along the mirrored axes
+          if (flm[i] & 1) { cx = -cx; sgn0 = T(-1); }
+          if (flm[i] & 2) { cy = -cy; sgn1 = T(-1); }
+          if (flm[i] & 4) { cm = -cm; sgn2 = T(-1); }
+        }
         const int ps = (cm == 1) ? sp : ((cm == -1) ? sn : sc);
         const int node = nodeo - cy * HX - cx;
         const T gy_ = ST::ld(&gy_r[i]);
@@ -474,7 +513,21 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
         const T Acoef = parS[ps][0][node];
         const T Bcoef = parS[ps][1][node];
         const T ia2 = parS[ps][NP - 1][node];
-        const T src = T(LP::W[i]) * (Bcoef + eC(i, ps, node));
+        T eCi;
+        if constexpr (MIR) {
+          // e_i' . C(x') with i' the mirror image of i
+          eCi = T(0);
+          if (LP::E[i][0] != 0) eCi += (sgn0 * T(LP::E[i][0])) * parS[ps][2][node];
+          if constexpr (DIM == 3) {
+            if (LP::E[i][1] != 0) eCi += (sgn1 * T(LP::E[i][1])) * parS[ps][3][node];
+            if (LP::E[i][2] != 0) eCi += (sgn2 * T(LP::E[i][2])) * parS[ps][4][node];
+          } else {
+            if (LP::E[i][1] != 0) eCi += (sgn2 * T(LP::E[i][1])) * parS[ps][3][node];
+          }
+        } else {
+          eCi = eC(i, ps, node);
+        }
+        const T src = T(LP::W[i]) * (Bcoef + eCi);
         if constexpr (OFF) {
           const T phx = phiS[rs(m - cm)][pco - cy * PX - cx];
           const T hs = Acoef * gx_ + src;
@@ -595,89 +648,94 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
   }
 }
 
-template <int K, int TY, class ST, bool IDS>
+
+// ---- launchers, instantiated once per value of MIR (one source file each) ----
+template <int K, int TY, class ST, bool IDS, bool MIR>
 static hipError_t launch_step_t(const SimDev &sd, const TileDev &tc, hipStream_t st) {
   const int nblocks = tc.tiles_x * tc.tiles_y * tc.nchunks;
   dim3 block(64, LatOf<K>::DIM == 3 ? TY : 1);
-  hipLaunchKernelGGL((step_kernel<K, TY, ST, IDS, false>), dim3(nblocks), block, 0, st, sd, tc, nullptr, nullptr, 0);
+  hipLaunchKernelGGL((step_kernel<K, TY, ST, IDS, false, MIR>), dim3(nblocks), block, 0, st, sd, tc, nullptr,
+                     nullptr, 0);
   return hipGetLastError();
 }
 
-template <int K, class ST, bool IDS>
+template <int K, class ST, bool IDS, bool MIR>
 static hipError_t launch_step_ty(const SimDev &sd, const TileDev &tc, hipStream_t st) {
   if constexpr (LatOf<K>::DIM == 2) {
-    return launch_step_t<K, 1, ST, IDS>(sd, tc, st);
+    return launch_step_t<K, 1, ST, IDS, MIR>(sd, tc, st);
   } else {
     switch (tc.ty) {
-      case 4: return launch_step_t<K, 4, ST, IDS>(sd, tc, st);
+      case 4: return launch_step_t<K, 4, ST, IDS, MIR>(sd, tc, st);
       case 8:
-        if constexpr (!std::is_same<ST, StF64>::value) return launch_step_t<K, 8, ST, IDS>(sd, tc, st);
+        if constexpr (!std::is_same<ST, StF64>::value) return launch_step_t<K, 8, ST, IDS, MIR>(sd, tc, st);
         return hipErrorInvalidValue;
       case 12:
-        if constexpr (!std::is_same<ST, StF64>::value) return launch_step_t<K, 12, ST, IDS>(sd, tc, st);
+        if constexpr (!std::is_same<ST, StF64>::value) return launch_step_t<K, 12, ST, IDS, MIR>(sd, tc, st);
         return hipErrorInvalidValue;
       default: return hipErrorInvalidValue;
     }
   }
 }
 
-template <int K, class ST>
+template <int K, class ST, bool MIR>
 static hipError_t launch_step_st(const SimDev &sd, const TileDev &tc, hipStream_t st) {
-  return sd.use_ids ? launch_step_ty<K, ST, true>(sd, tc, st) : launch_step_ty<K, ST, false>(sd, tc, st);
+  return sd.use_ids ? launch_step_ty<K, ST, true, MIR>(sd, tc, st) : launch_step_ty<K, ST, false, MIR>(sd, tc, st);
 }
 
-template <int K>
+template <int K, bool MIR>
 static hipError_t launch_step_k(int storage, const SimDev &sd, const TileDev &tc, hipStream_t st) {
   switch (storage) {
-    case 0: return launch_step_st<K, StF64>(sd, tc, st);
-    case 1: return launch_step_st<K, StF32>(sd, tc, st);
-    case 2: return launch_step_st<K, StF16>(sd, tc, st);
+    case 0: return launch_step_st<K, StF64, MIR>(sd, tc, st);
+    case 1: return launch_step_st<K, StF32, MIR>(sd, tc, st);
+    case 2: return launch_step_st<K, StF16, MIR>(sd, tc, st);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_step(int lattice, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st) {
+template <bool MIR>
+static hipError_t launch_step_m(int lattice, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st) {
   switch (lattice) {
-    case 0: return launch_step_k<0>(storage, sd, tc, st);
-    case 1: return launch_step_k<1>(storage, sd, tc, st);
-    case 2: return launch_step_k<2>(storage, sd, tc, st);
+    case 0: return launch_step_k<0, MIR>(storage, sd, tc, st);
+    case 1: return launch_step_k<1, MIR>(storage, sd, tc, st);
+    case 2: return launch_step_k<2, MIR>(storage, sd, tc, st);
   }
   return hipErrorInvalidValue;
 }
 
-template <class ST, bool IDS>
+template <class ST, bool IDS, bool MIR>
 static hipError_t launch_batch_t(const SimDev *sims, const BatchItem *items, int n_items, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((step_kernel<0, 1, ST, IDS, true>), dim3(grid), dim3(64), 0, st, SimDev{}, TileDev{}, sims, items,
-                     n_items);
+  hipLaunchKernelGGL((step_kernel<0, 1, ST, IDS, true, MIR>), dim3(grid), dim3(64), 0, st, SimDev{}, TileDev{}, sims,
+                     items, n_items);
   return hipGetLastError();
 }
 
-hipError_t launch_batch(int storage, bool ids, const SimDev *sims, const BatchItem *items, int n_items, int grid,
-                        hipStream_t st) {
+template <bool MIR>
+static hipError_t launch_batch_m(int storage, bool ids, const SimDev *sims, const BatchItem *items, int n_items,
+                                 int grid, hipStream_t st) {
   if (n_items < 1 || grid < 1) return hipErrorInvalidValue;
   switch (storage) {
-    case 0: return ids ? launch_batch_t<StF64, true>(sims, items, n_items, grid, st)
-                       : launch_batch_t<StF64, false>(sims, items, n_items, grid, st);
-    case 1: return ids ? launch_batch_t<StF32, true>(sims, items, n_items, grid, st)
-                       : launch_batch_t<StF32, false>(sims, items, n_items, grid, st);
-    case 2: return ids ? launch_batch_t<StF16, true>(sims, items, n_items, grid, st)
-                       : launch_batch_t<StF16, false>(sims, items, n_items, grid, st);
+    case 0: return ids ? launch_batch_t<StF64, true, MIR>(sims, items, n_items, grid, st)
+                       : launch_batch_t<StF64, false, MIR>(sims, items, n_items, grid, st);
+    case 1: return ids ? launch_batch_t<StF32, true, MIR>(sims, items, n_items, grid, st)
+                       : launch_batch_t<StF32, false, MIR>(sims, items, n_items, grid, st);
+    case 2: return ids ? launch_batch_t<StF16, true, MIR>(sims, items, n_items, grid, st)
+                       : launch_batch_t<StF16, false, MIR>(sims, items, n_items, grid, st);
   }
   return hipErrorInvalidValue;
 }
 
-template <class ST, bool IDS> static int batch_occupancy_t() {
+template <class ST, bool IDS, bool MIR> static int batch_occupancy_t() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<0, 1, ST, IDS, true>, 64, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<0, 1, ST, IDS, true, MIR>, 64, 0) != hipSuccess)
     return 0;
   return nb;
 }
 
-int batch_blocks_per_cu(int storage, bool ids) {
+template <bool MIR> static int batch_blocks_per_cu_m(int storage, bool ids) {
   switch (storage) {
-    case 0: return ids ? batch_occupancy_t<StF64, true>() : batch_occupancy_t<StF64, false>();
-    case 1: return ids ? batch_occupancy_t<StF32, true>() : batch_occupancy_t<StF32, false>();
-    case 2: return ids ? batch_occupancy_t<StF16, true>() : batch_occupancy_t<StF16, false>();
+    case 0: return ids ? batch_occupancy_t<StF64, true, MIR>() : batch_occupancy_t<StF64, false, MIR>();
+    case 1: return ids ? batch_occupancy_t<StF32, true, MIR>() : batch_occupancy_t<StF32, false, MIR>();
+    case 2: return ids ? batch_occupancy_t<StF16, true, MIR>() : batch_occupancy_t<StF16, false, MIR>();
   }
   return 0;
 }

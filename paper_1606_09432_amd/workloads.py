@@ -252,6 +252,17 @@ def paper3d(dendrite: str = "A", storage: str = "fp64", n: int = 351) -> SimConf
         seeds=[Seed(c, c, c, 10.0, 1)], tip_dir=(1, 0, 0))
 
 
+# The paper's symmetric run of dendrite B (Sec. 5): seed at the origin of a
+# 351^3 box, completed by symmetry about the planes XY, YZ and XZ, Delta = 0.25,
+# 1.5e5 steps in 98.54 h on 50 CPU cores.
+PAPER3D_OCTANT = (Aniso("cubic_hak", eps=0.0, gamma=-0.02), 150000, 98.54 * 3600, 50)
+
+
+def paper3d_octant(storage: str = "fp64", n: int = 351) -> SimConfig:
+    return paper3d("B", storage, n).replace(boundary="mirror_low", delta=0.25, aniso=[PAPER3D_OCTANT[0]],
+                                            seeds=[Seed(0.0, 0.0, 0.0, 10.0, 1)])
+
+
 def multi_3d(storage: str = "fp64", lattice: str = "D3Q19_D3Q7", gradient: str = "dd",
              shape=(48, 44, 40), boundary: str = "zero_flux") -> SimConfig:
     """A small 3D box with three crystals, each with its own anisotropy entry

@@ -85,6 +85,18 @@ def test_invalid_configs_rejected(lib, mutate, code):
     assert lib.lb_pf_last_error()
 
 
+def test_boundary_values(lib):
+    """LBPF_MIRROR_LOW (2) is a valid boundary; 3 is not."""
+    keep = []
+    b = C.c_size_t()
+    s = lb._to_struct(W.c0(n=32).replace(boundary="mirror_low"), keep)
+    assert s.boundary == 2
+    assert lib.lb_pf_workspace_bytes(C.byref(s), 1, C.byref(b)) == 0
+    s.boundary = 3
+    assert lib.lb_pf_workspace_bytes(C.byref(s), 1, C.byref(b)) == -1
+    assert "boundary" in lib.lb_pf_last_error().decode()
+
+
 def test_init_rejects_missing_workspace(lib):
     keep = []
     s = lb._to_struct(W.c0(n=32), keep)
