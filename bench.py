@@ -357,6 +357,33 @@ def run_paper3d(steps: int, warmup: int):
     return out
 
 
+def measure_copy(mib: int = 2048, reps: int = 10):
+    """Device-to-device copy bandwidth on the same GPU (the STREAM-copy
+    reference for the step's HBM roofline): bytes read + written per second."""
+    import torch
+
+    n = mib * (1 << 20)
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = 2 * n / (ms * 1e-3) / 1e9
+    print(f"[bench] copy: {mib} MiB in {ms:.3f} ms, {gbs:.0f} GB/s", file=sys.stderr, flush=True)
+    return {"value": gbs, "unit": "GB/s", "bytes_per_copy": 2 * n, "ms_per_copy": ms,
+            "kind": f"device-to-device copy of {mib} MiB (torch copy_), read + written bytes"}
+
+
 def cpu_baseline(cfg_full, sample_n: int, sample_steps: int):
     """The CPU FP64 oracle on a bounded sample: the same parameters on a
     sample_n^3 box around the seed, sample_steps steps."""
@@ -576,6 +603,8 @@ def main():
                          args.autotune)
             out["d3q15"][st] = {"value": rr["value"], "unit": "MLUPS", "ms_per_step": rr["ms_per_step"],
                                 "roofline": rr["roofline"], "tile_y_chunk": rr["tile"]}
+    if not args.only:
+        out["hbm_copy"] = measure_copy()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(W.c3("fp64", args.variant, n=args.n), args.cpu_sample, args.cpu_steps)

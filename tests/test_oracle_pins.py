@@ -199,6 +199,42 @@ def test_dd_closed_form_d3q15(oracle_mod):
     np.testing.assert_allclose(p[..., 2], pz, rtol=0, atol=1e-15)
 
 
+@pytest.mark.parametrize("lattice", ["D2Q9", "D3Q19", "D3Q15"])
+def test_upwind_directional_derivatives_through_the_moment(oracle_mod, lattice):
+    """Sec. 4.2 also names the first- and second-order upwind directional
+    derivatives.  Put through the weighted first moment (Eq. Grad_DF-Centree),
+    the first-order one, sum_i w_i e_i [phi(x + e_i) - phi(x)] / e^2, is the
+    central form exactly (sum_i w_i e_i = 0 and the lattice is symmetric), so
+    it needs no variant of its own: the oracle's DD gradient equals it.  The
+    second-order one, sum_i w_i e_i [4 phi(x + e_i) - phi(x + 2 e_i) - 3 phi(x)]
+    / (2 e^2), reaches two nodes and differs at O(dx^2) (not built)."""
+    E, W_, _opp, e2 = oracle_mod.lattice(lattice)
+    dim = 2 if lattice == "D2Q9" else 3
+    n = 12
+    if dim == 2:
+        cfg = W.c0(n=n)
+        shape = (n, n)
+    else:
+        cfg = W.small_3d(n=n).replace(boundary="periodic",
+                                      lattice="D3Q15_D3Q7" if lattice == "D3Q15" else "D3Q19_D3Q7")
+        shape = (n, n, n)
+    sim = oracle_mod.OracleSim(cfg)
+    rng = np.random.default_rng(13)
+    phi = rng.uniform(-1, 1, size=shape)
+    sim.set_fields(phi, np.zeros(shape))
+    p = sim.params()["p"]
+
+    def shifted(e, k=1):  # phi(x + k e) on the periodic box, numpy axes reversed
+        return np.roll(phi, tuple(-k * int(c) for c in e[:dim][::-1]), axis=tuple(range(dim)))
+
+    up1 = [sum(W_[i] * E[i][a] * (shifted(E[i]) - phi) for i in range(len(W_))) / e2 for a in range(dim)]
+    up2 = [sum(W_[i] * E[i][a] * (4 * shifted(E[i]) - shifted(E[i], 2) - 3 * phi) for i in range(len(W_)))
+           / (2 * e2) for a in range(dim)]
+    for a in range(dim):
+        np.testing.assert_allclose(p[..., a], up1[a], rtol=0, atol=1e-15)
+    assert max(np.abs(p[..., a] - up2[a]).max() for a in range(dim)) > 0.1
+
+
 # ---------------------------------------------------------------------------
 # P4: anisotropy and flux N (Sec. 2 Eq. TermesAnisotropes, Sec. 4.1).
 # ---------------------------------------------------------------------------
