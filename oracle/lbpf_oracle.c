@@ -535,10 +535,13 @@ static void pass_phi_lbe(orc_sim *S) {
 }
 
 /* Pass 4b (mirror_low only): g_i arriving at y from a source x = y - e_i
- * beyond a mirror plane.  In the symmetric domain that source holds the mirror
- * image of the node x' inside, with direction i' the mirror image of i, so the
- * update of Eq. LBE_Eq_Phase takes g_i'(x'), g^(0)_i'(x'), eta, Q and a_s^2 at
- * x' (w_i' = w_i). */
+ * beyond a mirror plane.  The state at x is the mirror image of the state at
+ * the node x' inside: phi, u and the index of x', the population g_i'(x') of
+ * the mirrored direction i', and the gradient p(x') with the mirrored axes
+ * negated.  The step's rules then give a_s, N and eta at x from that gradient
+ * (Sec. 2, Eq. TermesAnisotropes; Eq. LBE_RelaxationTime) and g^(0)_i(x) from
+ * N (Eq. Feq_Phase); Q is that of x'.  For an anisotropy symmetric about the
+ * plane these are a_s(x') and the mirror image of N(x'). */
 static void pass_phi_mirror(orc_sim *S) {
   if (!S->cfg.mirror_low) return;
   const lat_t *L = &S->lp;
@@ -553,10 +556,17 @@ static void pass_phi_mirror(orc_sim *S) {
         const long c = partner_sym(S, x, y, z, L->e[i], -1, &fl);
         if (c < 0 || fl == 0) continue;
         const int j = mirror_dir(L, i, fl);
-        const double a2 = S->a[c] * S->a[c];
+        double pg[3], ag, Ng[3];
+        for (int k = 0; k < 3; ++k) pg[k] = (fl >> k & 1) ? -S->p[3 * c + k] : S->p[3 * c + k];
+        orc_flux(entry_for(S, S->id[c]), pg, &ag, Ng);
+        const double a2 = ag * ag;
+        const double eta = a2 * S->kphi + 0.5;
+        const int *e = L->e[i];
+        const double eN = ((double)e[0] * Ng[0] + (double)e[1] * Ng[1]) + (double)e[2] * Ng[2];
+        const double geq_x = L->w[i] * (S->phi[c] - S->kphi * eN);
         const double gx = S->g[(long)j * N + c];
         const double gy = S->g[(long)i * N + d];
-        const double rhs = gx - (1.0 - a2) * gy - (gx - geq(S, j, c)) / S->eta[c] + L->w[j] * S->Q[c] * S->s;
+        const double rhs = gx - (1.0 - a2) * gy - (gx - geq_x) / eta + L->w[i] * S->Q[c] * S->s;
         S->gn[(long)i * N + d] = rhs / a2;
       }
     }
