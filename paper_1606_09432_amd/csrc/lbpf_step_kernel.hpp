@@ -75,8 +75,9 @@ template <int DIM, int TY, class ST> constexpr int min_waves() {
 // ... (G = grid size): static balance, no atomics, no per-step reset.
 // MIR = true adds the mirror planes through node 0 (SimDev::mirror): a source
 // x = y - e_i beyond one is the mirror node x' inside, whose population is the
-// mirror image i' of i and whose coefficients give the update, with the
-// component of e . C taken along i'.
+// mirror image i' of i; its coefficients are those of the ghost node at x
+// (computed from the mirrored rings: the mirror image of x', so that
+// e_i . C(x) = e_i' . C(x')).
 template <int K, int TY, class ST, bool IDS, bool BATCH, bool MIR>
 __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(min_waves<LatOf<K>::DIM, TY, ST>(), 8))) void
 step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const BatchItem *__restrict__ items,
@@ -183,10 +184,15 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
     // box coordinates of coefficient node (hx, hy) of plane pm; false when the
     // node is never pulled from (outside the box, or beyond its one-node halo).
     // The coordinates returned are always inside the box (clamped when invalid).
-    auto node_at = [&](int hx, int hy, int pm, int &gx, int &gy, int &gm) -> bool {
+    // A ghost node at -1 beyond a mirror plane is valid: it holds the mirror
+    // image of the node at +1, whose coordinates are returned, with bit k of
+    // mir set for each mirrored axis (0 x, 1 yp, 2 m); a pull from beyond the
+    // plane then takes the ghost's coefficients like those of any other node.
+    auto node_at = [&](int hx, int hy, int pm, int &gx, int &gy, int &gm, int &mir) -> bool {
       gx = x0 - 1 + hx;
       gy = (DIM == 3) ? y0 - 1 + hy : 0;
       gm = pm;
+      mir = 0;
       bool ok;
       if (per) {
         ok = gx <= sd.nx && (DIM == 2 || gy <= sd.nyp);
@@ -195,6 +201,15 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
         gm = wrapc(gm, sd.nm);
       } else {
         ok = in_range(gx, sd.nx) && (DIM == 2 || in_range(gy, sd.nyp)) && in_range(gm, sd.nm);
+        if constexpr (MIR) {
+          if (sd.mirror) {
+            ok = gx >= -1 && gx < sd.nx && (DIM == 2 || (gy >= -1 && gy < sd.nyp)) && gm >= -1 && gm < sd.nm;
+            mir = (gx == -1 ? 1 : 0) | (DIM == 3 && gy == -1 ? 2 : 0) | (gm == -1 ? 4 : 0);
+            gx = abs(gx);
+            gy = abs(gy);
+            gm = abs(gm);
+          }
+        }
       }
       gx = min(max(gx, 0), sd.nx - 1);
       gy = (DIM == 3) ? min(max(gy, 0), sd.nyp - 1) : 0;
@@ -261,6 +276,9 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       const int gy = (DIM == 3) ? ghost(ry, sd.nyp, per) : 0;
       off = (unsigned)gy * (unsigned)pitch + (unsigned)gx;
       out = !per && (!in_range(rx, sd.nx) || (DIM == 3 && !in_range(ry, sd.nyp)));
+      if constexpr (MIR) {
+        if (sd.mirror) out = rx >= sd.nx || (DIM == 3 && ry >= sd.nyp);  // mirrored below 0
+      }
     };
     if constexpr (!OFF) {
   #pragma unroll
@@ -268,7 +286,10 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
     }
     auto ring_fetch = [&](int pm) {
       const int gm = ghost(pm, sd.nm, per);  // pm is always within [-2, nm + 1]
-      const bool mout = !per && !in_range(pm, sd.nm);
+      bool mout = !per && !in_range(pm, sd.nm);
+      if constexpr (MIR) {
+        if (sd.mirror) mout = pm >= sd.nm;  // mirrored below 0
+      }
       const unsigned mo = (unsigned)gm * (unsigned)mstride;
   #pragma unroll
       for (int j = 0; j < NLOAD; ++j) {
@@ -306,8 +327,8 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
     // ---- heat populations gathered by a coefficient node (prefetched) ---------
     S kv_o_c[QU], kv_h_c[QU], kv_o_n[QU], kv_h_n[QU];
     auto gather_fetch = [&](int hx, int hy, int pm, S(&kv)[QU]) {
-      int gx, gy, gm;
-      node_at(hx, hy, pm, gx, gy, gm);
+      int gx, gy, gm, mir;
+      node_at(hx, hy, pm, gx, gy, gm, mir);  // a ghost gathers as its mirror node
       if (xy_in2 && pm >= 1 && pm + 1 < sd.nm) {
         const unsigned ib = lin(sd, gx, gy, gm) * (unsigned)sizeof(S);
   #pragma unroll
@@ -331,8 +352,8 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
 
     // ---- A: coefficients of node (hx, hy) of plane pm into coefficient slot ps
     auto param_node = [&](int hx, int hy, int pm, int ps, const S(&kv)[QU], bool own_node) {
-      int gx, gy, gm;
-      if (!node_at(hx, hy, pm, gx, gy, gm)) return;
+      int gx, gy, gm, mir;
+      if (!node_at(hx, hy, pm, gx, gy, gm, mir)) return;
       const int pc = (hy + PYO) * PX + (hx + 1);  // node in the ring
       const int sl0 = rs(pm);
       const T phc = phiS[sl0][pc];
@@ -395,6 +416,12 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
           unsigned src;
           int d, ox, oy, om;
           heat_src(gx, gy, gm, i, src, d, ox, oy, om);
+          if constexpr (MIR) {
+            // a ghost node: its mirror node's source, seen from the ghost
+            if (mir & 1) ox = -ox;
+            if (mir & 2) oy = -oy;
+            if (mir & 4) om = -om;
+          }
           const float usrc = usS[rs4(pm + om)][pc + oy * PX + ox];
           fd[i] = T(LU::W[i]) * (usrc - us_self) + kvv;
         } else {
@@ -453,29 +480,31 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       const unsigned iyb = iy * (unsigned)sizeof(S);
       S gy_r[QP], gx_r[QP];
       bool unk[QP];
-      int flm[QP];  // mirrored axes of each source (bit 0 x, 1 yp, 2 m)
       // one batch of loads: g_i(y) and g_i(y - e_i)
-      if (xy_in1 && m >= 1 && m + 1 < sd.nm) {
+      const bool fast = xy_in1 && m >= 1 && m + 1 < sd.nm;
+      auto load_fast = [&]() {
   #pragma unroll
         for (int i = 0; i < QP; ++i) {
           unk[i] = false;
-          flm[i] = 0;
           gy_r[i] = ldb(gfield(i), iyb);
           gx_r[i] = ldb(gfield(i), iyb + boff_of(ex<LP, DIM>(i), ey<LP, DIM>(i), em<LP, DIM>(i), sizeof(S)));
         }
-      } else {
+      };
+      auto load_generic = [&](auto flip) {
+        constexpr bool FLIP = decltype(flip)::value;
   #pragma unroll
         for (int i = 0; i < QP; ++i) {
           const int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
           int sx = gx_o - cx, sy = gy_o - cy, sm = m - cm;
-          flm[i] = 0;
-          if constexpr (MIR) {
-            if (sd.mirror) {
-              flm[i] = (sx < 0 ? 1 : 0) | (sy < 0 ? 2 : 0) | (sm < 0 ? 4 : 0);
-              sx = abs(sx);
-              sy = abs(sy);
-              sm = abs(sm);
-            }
+          int fl = 0;  // mirrored axes of the source (bit 0 x, 1 yp, 2 m)
+          if constexpr (FLIP) {
+            // only a component +1 can cross a plane through node 0: the
+            // flags of the other components are zero at compile time
+            const bool fx = cx == 1 && gx_o == 0, fy = DIM == 3 && cy == 1 && gy_o == 0, fm = cm == 1 && m == 0;
+            fl = (fx ? 1 : 0) | (fy ? 2 : 0) | (fm ? 4 : 0);
+            if (fx) sx = 1;
+            if (fy) sy = 1;
+            if (fm) sm = 1;
           }
           if (per) {
             sx = wrapc(sx, sd.nx);
@@ -487,55 +516,57 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
           }
           const unsigned isrc = unk[i] ? iy : lin(sd, sx, sy, sm);
           gy_r[i] = ldb(gfield(i), iyb);
-          if constexpr (MIR) {
-            gx_r[i] = ldb(gfield(mirror_sel<LP, DIM>(i, flm[i])), isrc * (unsigned)sizeof(S));
+          if constexpr (FLIP) {
+            gx_r[i] = ldb(gfield(mirror_sel<LP, DIM>(i, fl)), isrc * (unsigned)sizeof(S));
           } else {
             gx_r[i] = ldb(gfield(i), isrc * (unsigned)sizeof(S));
           }
         }
-      }
-      const T phy = phiS[rs(m)][pco];
+      };
+      T phy;
       T d[QP];
-  #pragma unroll
-      for (int i = 0; i < QP; ++i) {
-        int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
-        T sgn0 = T(1), sgn1 = T(1), sgn2 = T(1);
-        if constexpr (MIR) {
-          // a mirrored source sits at y + e_i along the mirrored axes
-          if (flm[i] & 1) { cx = -cx; sgn0 = T(-1); }
-          if (flm[i] & 2) { cy = -cy; sgn1 = T(-1); }
-          if (flm[i] & 4) { cm = -cm; sgn2 = T(-1); }
-        }
-        const int ps = (cm == 1) ? sp : ((cm == -1) ? sn : sc);
-        const int node = nodeo - cy * HX - cx;
-        const T gy_ = ST::ld(&gy_r[i]);
-        const T gx_ = ST::ld(&gx_r[i]);
-        const T Acoef = parS[ps][0][node];
-        const T Bcoef = parS[ps][1][node];
-        const T ia2 = parS[ps][NP - 1][node];
-        T eCi;
-        if constexpr (MIR) {
-          // e_i' . C(x') with i' the mirror image of i
-          eCi = T(0);
-          if (LP::E[i][0] != 0) eCi += (sgn0 * T(LP::E[i][0])) * parS[ps][2][node];
-          if constexpr (DIM == 3) {
-            if (LP::E[i][1] != 0) eCi += (sgn1 * T(LP::E[i][1])) * parS[ps][3][node];
-            if (LP::E[i][2] != 0) eCi += (sgn2 * T(LP::E[i][2])) * parS[ps][4][node];
+      // the pulls (a source beyond a mirror plane is its ghost coefficient node)
+      auto pull = [&]() {
+    #pragma unroll
+        for (int i = 0; i < QP; ++i) {
+          const int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
+          const int ps = (cm == 1) ? sp : ((cm == -1) ? sn : sc);
+          const int node = nodeo - cy * HX - cx;
+          const T gy_ = ST::ld(&gy_r[i]);
+          const T gx_ = ST::ld(&gx_r[i]);
+          const T Acoef = parS[ps][0][node];
+          const T Bcoef = parS[ps][1][node];
+          const T ia2 = parS[ps][NP - 1][node];
+          const T src = T(LP::W[i]) * (Bcoef + eC(i, ps, node));
+          if constexpr (OFF) {
+            const T phx = phiS[rs(m - cm)][pco - cy * PX - cx];
+            const T hs = Acoef * gx_ + src;
+            d[i] = gy_ + ia2 * (T(LP::W[i]) * (phx - phy) + hs - gy_);
           } else {
-            if (LP::E[i][1] != 0) eCi += (sgn2 * T(LP::E[i][1])) * parS[ps][3][node];
+            const T gs = Acoef * gx_ + src;
+            d[i] = gy_ + ia2 * (gs - gy_);
           }
-        } else {
-          eCi = eC(i, ps, node);
         }
-        const T src = T(LP::W[i]) * (Bcoef + eCi);
-        if constexpr (OFF) {
-          const T phx = phiS[rs(m - cm)][pco - cy * PX - cx];
-          const T hs = Acoef * gx_ + src;
-          d[i] = gy_ + ia2 * (T(LP::W[i]) * (phx - phy) + hs - gy_);
-        } else {
-          const T gs = Acoef * gx_ + src;
-          d[i] = gy_ + ia2 * (gs - gy_);
-        }
+      };
+      if constexpr (MIR) {
+        // only tiles on a mirror plane load mirrored populations; the pulls
+        // take the ghost coefficient nodes beyond the plane as they are
+        const bool low = sd.mirror && (x0 == 0 || (DIM == 3 && y0 == 0) || m == 0);
+        if (fast)
+          load_fast();
+        else if (low)
+          load_generic(std::true_type{});
+        else
+          load_generic(std::false_type{});
+        phy = phiS[rs(m)][pco];
+        pull();
+      } else {
+        if (fast)
+          load_fast();
+        else
+          load_generic(std::false_type{});
+        phy = phiS[rs(m)][pco];
+        pull();
       }
       if (walls) {
         // bounce-back: an unknown incoming population takes the opposite one; if
