@@ -5,6 +5,7 @@ itself: the expected values are printed numbers from the paper (fixtures under
 ``tests/golden/``), closed forms, exact invariants, special cases that reduce
 to a textbook scheme written independently below, or brute-force derivatives.
 """
+import itertools
 import json
 import math
 import os
@@ -821,6 +822,75 @@ def test_tip_position_definition(oracle_mod):
     ph[10, 10, 10] = -0.5  # crossing between k = 5 and k = 6 at 5 + 1/1.5
     s3.set_fields(ph, np.zeros_like(ph))
     assert abs(s3.diagnostics()["tip_position"] - (5 + 1 / 1.5) * math.sqrt(3)) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# P13: crystal shapes.  The tips point where a_s is largest: four of them for
+# q = 4 in 2D (along the axes for phi0 = 0, along the diagonals for pi/4), six
+# for q = 6; in 3D six <100> tips for (eps1, eps2) = (0.1, 0) and twelve <110>
+# tips for (0, -0.05) of Eq. As_MatSci.  Eight <111> tips need a longer growth
+# than the oracle affords here: the paper's three dendrites of Sec. 5 (six,
+# twelve and eight tips) run on the GPU path (tests/test_gpu_parity.py).
+# ---------------------------------------------------------------------------
+def _ray_radius(phi, c, d):
+    """Largest linearly interpolated phi = 0 crossing along c + k d (lattice
+    units; d in (x, y, z), numpy axes reversed)."""
+    dim = phi.ndim
+    step = math.sqrt(sum(v * v for v in d[:dim]))
+    best, k = -1.0, 0
+    while True:
+        a = [c + k * d[j] for j in range(dim)]
+        b = [c + (k + 1) * d[j] for j in range(dim)]
+        if any(not 0 <= v < phi.shape[dim - 1 - j] for j, v in enumerate(b)):
+            return best
+        pa, pb = phi[tuple(a[::-1])], phi[tuple(b[::-1])]
+        if pa > 0 >= pb:
+            best = (k + pa / (pa - pb)) * step
+        k += 1
+
+
+def _polar_tips(phi, c, nang=360):
+    """Angles (degrees) of the local maxima of the phi = 0 radius around c."""
+    from scipy.ndimage import map_coordinates
+    ang = np.linspace(0, 2 * np.pi, nang, endpoint=False)
+    dr = 0.25
+    r = np.arange(0, c - 1, dr)
+    R = np.empty(nang)
+    for j, a in enumerate(ang):
+        v = map_coordinates(phi, [c + r * np.sin(a), c + r * np.cos(a)], order=3)
+        k = np.where((v[:-1] > 0) & (v[1:] <= 0))[0][-1]
+        R[j] = r[k] + v[k] / (v[k] - v[k + 1]) * dr
+    Rs = np.convolve(np.r_[R[-5:], R, R[:5]], np.ones(11) / 11, mode="valid")
+    return [round(float(np.degrees(ang[i]))) for i in range(nang)
+            if Rs[i] > Rs[i - 1] and Rs[i] >= Rs[(i + 1) % nang]]
+
+
+@pytest.mark.parametrize("q,phi0,tips", [(4, 0.0, [0, 90, 180, 270]), (4, math.pi / 4, [45, 135, 225, 315]),
+                                         (6, 0.0, [0, 60, 120, 180, 240, 300])])
+def test_tip_count_2d(oracle_mod, q, phi0, tips):
+    cfg = W.c0().replace(aniso=[W.Aniso("sectoral", eps=0.05, q=q, phi0=phi0)])
+    sim = oracle_mod.OracleSim(cfg)
+    sim.step(W.C0_STEPS)
+    got = _polar_tips(sim.phi(), cfg.nx // 2)
+    assert len(got) == len(tips)
+    assert all(min(abs(g - t), 360 - abs(g - t)) <= 2 for g, t in zip(sorted(got), tips))
+
+
+@pytest.mark.parametrize("variant,family,count", [("100", 1, 6), ("110", 2, 12)])
+def test_tip_count_3d(oracle_mod, variant, family, count):
+    """Families of lattice rays by the number of nonzero components (1: <100>,
+    2: <110>, 3: <111>); the preferred family reaches farther than all others."""
+    n = 64
+    sim = oracle_mod.OracleSim(W.c3("fp64", variant, n=n, radius=6.0))
+    sim.step(300)
+    phi = sim.phi()
+    radii = {1: [], 2: [], 3: []}
+    for d in itertools.product((-1, 0, 1), repeat=3):
+        if any(d):
+            radii[sum(map(abs, d))].append(_ray_radius(phi, n // 2, d))
+    assert len(radii[family]) == count
+    others = [r for k, v in radii.items() if k != family for r in v]
+    assert min(radii[family]) > max(others) + 0.02
 
 
 # ---------------------------------------------------------------------------
