@@ -499,8 +499,8 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--n", type=int, default=512, help="grid side (the workload is 512)")
     ap.add_argument("--variant", default="100", choices=["100", "111", "110"])
     ap.add_argument("--autotune", action="store_true")
