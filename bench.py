@@ -234,6 +234,28 @@ def _cubic_sample(phi, x, y):
     return out
 
 
+def rotation_difference(phi, centre, degrees=60.0, margin=3):
+    """phi^rot - phi over the box (Sec. 4.2, Fig. Differences-Fields): phi^rot
+    is phi turned by `degrees` about `centre`, phi^rot(x) = phi(c + R(-theta)
+    (x - c)), sampled by cubic convolution.  Nodes whose rotated point leaves
+    the box (less `margin`) are skipped.  Returns (max, min, x of the max,
+    x of the min); phi is [y][x]."""
+    import numpy as np
+
+    ny, nx = phi.shape
+    cx, cy = centre
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64), indexing="ij")
+    t = math.radians(degrees)
+    xs = cx + math.cos(t) * (x - cx) + math.sin(t) * (y - cy)
+    ys = cy - math.sin(t) * (x - cx) + math.cos(t) * (y - cy)
+    ok = (xs >= margin) & (xs <= nx - 1 - margin) & (ys >= margin) & (ys <= ny - 1 - margin)
+    d = np.full(phi.shape, np.nan)
+    d[ok] = _cubic_sample(phi, xs[ok], ys[ok]) - phi[ok]
+    imax, imin = np.nanargmax(d), np.nanargmin(d)
+    at = lambda i: (int(i % nx), int(i // nx))
+    return float(np.nanmax(d)), float(np.nanmin(d)), at(imax), at(imin)
+
+
 def tip_radius(phi, cx, cy, theta, rmax=40.0, dr=0.125):
     """Distance from (cx, cy) to the phi = 0 crossing along the ray of angle
     theta (the first sign change from solid to liquid, linearly interpolated)."""
@@ -327,6 +349,8 @@ def run_isotropy(steps: int, storage: str):
         c = cfgs[k].seeds[0]
         out[f"err_l2_{name}"] = profile_l2_error(phi, (c.x, c.y))
         out[f"tip_{name}"] = sim.diagnostics()[k]["tip_position"]
+        dmax, dmin, xmax, xmin = rotation_difference(phi, (c.x, c.y))
+        out[f"rot60_{name}"] = {"max": dmax, "min": dmin, "at_max": xmax, "at_min": xmin}
     out["cd_over_dd"] = out["err_l2_cd"] / out["err_l2_dd"]
     return out
 

@@ -474,13 +474,28 @@ def test_e2_parity_window(gpu, oracle_mod, grad):
 def test_e2_isotropy_dd_vs_cd(gpu):
     """Full length (1e5 steps): the profiles along n_a = (1, 0) and
     n_b = (1/2, -sqrt(3)/2) differ far less with directional derivatives than
-    with central differences (the paper reports 3.04e-3 and 1.71e-1)."""
+    with central differences (the paper reports 3.04e-3 and 1.71e-1), and so
+    does the solution from its own 60-degree rotation: the extremes of
+    phi^rot - phi are printed as 1.446 / -1.454 (central differences) and
+    0.1 / -0.103 (directional derivatives), Sec. 4.2."""
+    import json
+    import os
+
     import bench
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    gold = gold["dd_vs_fd_isotropy_experiment"]
     _say(f"isotropy comparison, DD and CD batched, {W.E2_STEPS} steps")
     r = bench.run_isotropy(W.E2_STEPS, "fp64")
     _say(f"  {r}")
     assert r["err_l2_dd"] < 1e-2
     assert r["cd_over_dd"] >= 10
+    fd = max(r["rot60_cd"]["max"], -r["rot60_cd"]["min"])
+    dd = max(r["rot60_dd"]["max"], -r["rot60_dd"]["min"])
+    fd_paper = max(abs(v) for v in gold["tip_diff_fd"])
+    dd_paper = max(abs(v) for v in gold["tip_diff_dd"])
+    assert abs(fd - fd_paper) <= 0.1 * fd_paper
+    assert 0.5 * dd_paper <= dd <= 2.0 * dd_paper
+    assert fd / dd >= 7
 
 
 # ---------------------------------------------------------------------------
