@@ -403,7 +403,7 @@ static void pass_gradient(orc_sim *S, const double *phi) {
     for (int x = 0; x < S->nx; ++x) {
       const long c = nid(S, x, y, z);
       double pv[3];
-      if (S->cfg.grad_cd) {
+      if (S->cfg.grad_cd == 1) {
         /* central differences along the axes (Sec. 4.2) */
         for (int k = 0; k < 3; ++k) {
           if (k == 2 && S->cfg.dim == 2) {
@@ -417,12 +417,20 @@ static void pass_gradient(orc_sim *S, const double *phi) {
         }
       } else {
         /* directional derivative along each e_i (Eq. Def_DeriveeDirectionnelle),
-         * then grad = (1/e^2) sum_i w_i e_i (e_i . grad) (Eq. Grad_DF-Centree) */
+         * or its second-order upwind (biased) form of Sec. 4.2,
+         * [-phi(x + 2 e_i) + 4 phi(x + e_i) - 3 phi(x)] / 2, then
+         * grad = (1/e^2) sum_i w_i e_i (e_i . grad) (Eq. Grad_DF-Centree) */
         double dd[19];
         dd[0] = 0.0;
         for (int i = 1; i < L->q; ++i) {
           const int *e = L->e[i];
           const double fp = phi[nid(S, ghost(x + e[0], S->nx, per), ghost(y + e[1], S->ny, per), ghost(z + e[2], S->nz, per))];
+          if (S->cfg.grad_cd == 2) {
+            const double fpp = phi[nid(S, ghost(x + 2 * e[0], S->nx, per), ghost(y + 2 * e[1], S->ny, per),
+                                       ghost(z + 2 * e[2], S->nz, per))];
+            dd[i] = (-fpp + 4.0 * fp - 3.0 * phi[c]) / 2.0;
+            continue;
+          }
           const double fm = phi[nid(S, ghost(x - e[0], S->nx, per), ghost(y - e[1], S->ny, per), ghost(z - e[2], S->nz, per))];
           dd[i] = (fp - fm) / 2.0;
         }

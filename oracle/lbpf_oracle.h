@@ -50,7 +50,8 @@ typedef struct {
   int32_t dim;          /* 2: D2Q9 phi + D2Q5 u;  3: D3Q19 (or D3Q15, q_phi) phi + D3Q7 u */
   int32_t nx, ny, nz;   /* nz must be 1 when dim == 2 */
   int32_t periodic;     /* 1 periodic box, 0 zero flux (bounce-back, Eq. Bounce-Back) */
-  int32_t grad_cd;      /* 0 directional derivatives (Eq. Grad_DF-Centree), 1 central differences */
+  int32_t grad_cd;      /* 0 directional derivatives (Eq. Grad_DF-Centree), 1 central differences,
+                           2 second-order upwind directional derivatives (Sec. 4.2) */
   int32_t use_ids;      /* 1: crystal index field I(x,t) selects the anisotropy entry (Sec. 4.3) */
   double W0, tau0, lambda, kappa, delta, dx, dt, xi;
   int32_t n_aniso;

@@ -112,7 +112,7 @@ class OracleSim:
         c.nx, c.ny, c.nz = cfg.nx, cfg.ny, cfg.nz
         c.periodic = 1 if cfg.boundary == "periodic" else 0
         c.mirror_low = 1 if cfg.boundary == "mirror_low" else 0
-        c.grad_cd = 1 if cfg.gradient == "cd" else 0
+        c.grad_cd = {"dd": 0, "cd": 1, "up2": 2}[cfg.gradient]
         c.use_ids = 1 if cfg.use_ids else 0
         c.W0, c.tau0, c.lam, c.kappa = cfg.W0, cfg.tau0, cfg.lam, cfg.kappa
         c.delta, c.dx, c.dt, c.xi = cfg.delta, cfg.dx, cfg.dt, cfg.xi

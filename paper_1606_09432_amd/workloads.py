@@ -27,7 +27,7 @@ import numpy as np
 
 LATTICES = ("D2Q9_D2Q5", "D3Q19_D3Q7", "D3Q15_D3Q7")
 BOUNDARIES = ("periodic", "zero_flux", "mirror_low")
-GRADIENTS = ("dd", "cd")
+GRADIENTS = ("dd", "cd", "up2")
 STORAGES = ("fp64", "fp32", "fp16")
 ANISO_KINDS = ("iso", "sectoral", "cubic", "cubic_hak", "cubic_s")
 

@@ -121,7 +121,7 @@ def _quadratic(shape, rng):
     return phi, grad
 
 
-@pytest.mark.parametrize("grad", ["dd", "cd"])
+@pytest.mark.parametrize("grad", ["dd", "cd", "up2"])
 @pytest.mark.parametrize("dim", [2, 3])
 def test_gradient_exact_for_quadratics(oracle_mod, grad, dim):
     rng = np.random.default_rng(11)
@@ -135,7 +135,8 @@ def test_gradient_exact_for_quadratics(oracle_mod, grad, dim):
     phi, g = _quadratic(shape, rng)
     sim.set_fields(phi, np.zeros(shape))
     p = sim.params()["p"]
-    inner = tuple(slice(1, -1) for _ in shape)
+    r = 2 if grad == "up2" else 1  # away from the mirrored ghosts
+    inner = tuple(slice(r, -r) for _ in shape)
     # numpy axis order is (z, y, x) / (y, x); p is (x, y, z)
     for comp in range(dim):
         axis = dim - 1 - comp
@@ -155,6 +156,26 @@ def test_dd_closed_form_d2q9(oracle_mod):
     py = (s(1, 0) - s(-1, 0)) / 3 + (s(1, 1) + s(1, -1) - s(-1, 1) - s(-1, -1)) / 12
     np.testing.assert_allclose(p[..., 0], px, rtol=0, atol=1e-15)
     np.testing.assert_allclose(p[..., 1], py, rtol=0, atol=1e-15)
+
+
+def test_up2_closed_form_d2q9(oracle_mod):
+    """Second-order upwind directional derivatives (Sec. 4.2) through the
+    moment on D2Q9: each central pair difference f(x + e) - f(x - e) becomes
+    2 [f(x + e) - f(x - e)] - [f(x + 2e) - f(x - 2e)] / 2, so
+    p_x = [2(E - W) - (EE - WW)/2]/3 + [2(NE + SE - NW - SW) - (NE2 + SE2 - NW2 - SW2)/2]/12."""
+    cfg = W.c0(n=24, gradient="up2")
+    sim = oracle_mod.OracleSim(cfg)
+    rng = np.random.default_rng(15)
+    phi = rng.uniform(-1, 1, size=(24, 24))
+    sim.set_fields(phi, np.zeros_like(phi))
+    p = sim.params()["p"]
+    s = lambda dy, dx: np.roll(np.roll(phi, -dy, axis=0), -dx, axis=1)  # phi(x+dx, y+dy)
+    px = (2 * (s(0, 1) - s(0, -1)) - (s(0, 2) - s(0, -2)) / 2) / 3 + (
+        2 * (s(1, 1) + s(-1, 1) - s(1, -1) - s(-1, -1)) - (s(2, 2) + s(-2, 2) - s(2, -2) - s(-2, -2)) / 2) / 12
+    py = (2 * (s(1, 0) - s(-1, 0)) - (s(2, 0) - s(-2, 0)) / 2) / 3 + (
+        2 * (s(1, 1) + s(1, -1) - s(-1, 1) - s(-1, -1)) - (s(2, 2) + s(2, -2) - s(-2, 2) - s(-2, -2)) / 2) / 12
+    np.testing.assert_allclose(p[..., 0], px, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(p[..., 1], py, rtol=0, atol=1e-14)
 
 
 def test_dd_closed_form_d3q19(oracle_mod):
@@ -208,7 +229,7 @@ def test_upwind_directional_derivatives_through_the_moment(oracle_mod, lattice):
     central form exactly (sum_i w_i e_i = 0 and the lattice is symmetric), so
     it needs no variant of its own: the oracle's DD gradient equals it.  The
     second-order one, sum_i w_i e_i [4 phi(x + e_i) - phi(x + 2 e_i) - 3 phi(x)]
-    / (2 e^2), reaches two nodes and differs at O(dx^2) (not built)."""
+    / (2 e^2), reaches two nodes and differs at O(dx^2): the gradient "up2"."""
     E, W_, _opp, e2 = oracle_mod.lattice(lattice)
     dim = 2 if lattice == "D2Q9" else 3
     n = 12
@@ -234,6 +255,12 @@ def test_upwind_directional_derivatives_through_the_moment(oracle_mod, lattice):
     for a in range(dim):
         np.testing.assert_allclose(p[..., a], up1[a], rtol=0, atol=1e-15)
     assert max(np.abs(p[..., a] - up2[a]).max() for a in range(dim)) > 0.1
+    # the second-order form is the oracle's gradient "up2"
+    sim2 = oracle_mod.OracleSim(cfg.replace(gradient="up2"))
+    sim2.set_fields(phi, np.zeros(shape))
+    p2 = sim2.params()["p"]
+    for a in range(dim):
+        np.testing.assert_allclose(p2[..., a], up2[a], rtol=0, atol=1e-14)
 
 
 # ---------------------------------------------------------------------------
@@ -538,7 +565,7 @@ def test_planar_profile_second_order(oracle_mod, Dphi):
 # P11: exact 90 degree rotation invariance with directional derivatives and with
 # central differences (both lattice-covariant), on periodic and walled boxes.
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("grad", ["dd", "cd"])
+@pytest.mark.parametrize("grad", ["dd", "cd", "up2"])
 @pytest.mark.parametrize("boundary", ["periodic", "zero_flux"])
 def test_rotation_invariance_2d(oracle_mod, grad, boundary):
     n = 48 if boundary == "periodic" else 49
