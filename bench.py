@@ -317,7 +317,7 @@ def run_orientation_spread(storage: str, n_orient: int = 10, side: int = 400, st
     return out
 
 
-def run_isotropy(steps: int, storage: str):
+def run_isotropy(steps: int, storage: str, with_up2: bool = True):
     """The isotropy comparison of Sec. 4.2 (six-fold a_s, 800^2): the DD and CD
     runs advance together as one batched ensemble; prints Err_l2 of each and
     the throughput."""
@@ -352,6 +352,21 @@ def run_isotropy(steps: int, storage: str):
         dmax, dmin, xmax, xmin = rotation_difference(phi, (c.x, c.y))
         out[f"rot60_{name}"] = {"max": dmax, "min": dmin, "at_max": xmax, "at_min": xmin}
     out["cd_over_dd"] = out["err_l2_cd"] / out["err_l2_dd"]
+    sim.close()
+    del sim
+    if with_up2:
+        # the second-order upwind directional derivatives (Sec. 4.2) through the
+        # same moment: a single simulation (not batched)
+        cfg = W.e2("up2", storage=storage)
+        one = lb.Simulation(cfg)
+        one.step(steps)
+        phi = one.fields()[0].cpu().numpy()
+        c = cfg.seeds[0]
+        out["err_l2_up2"] = profile_l2_error(phi, (c.x, c.y))
+        out["tip_up2"] = one.diagnostics()[0]["tip_position"]
+        dmax, dmin, xmax, xmin = rotation_difference(phi, (c.x, c.y))
+        out["rot60_up2"] = {"max": dmax, "min": dmin, "at_max": xmax, "at_min": xmin}
+        one.close()
     return out
 
 

@@ -77,9 +77,16 @@ extern "C" {
 #define LBPF_PERIODIC 0
 #define LBPF_ZERO_FLUX 1
 #define LBPF_MIRROR_LOW 2
-/* Gradient of phi: directional derivatives (Eq. Grad_DF-Centree) or central differences. */
+/* Gradient of phi: directional derivatives (Eq. Grad_DF-Centree) or central
+ * differences.  LBPF_GRAD_UP2 puts the second-order upwind (biased)
+ * directional derivatives of Sec. 4.2, [-phi(x+2e) + 4 phi(x+e) - 3 phi(x)]/2,
+ * through the same moment (the first-order upwind form through it equals
+ * LBPF_GRAD_DD); it is implemented for single simulations on 4-row tiles in
+ * 3D, without the index field or mirror planes, with every extent >= 4
+ * (LBPF_ERR_UNSUPPORTED / LBPF_ERR_ARG otherwise). */
 #define LBPF_GRAD_DD 0
 #define LBPF_GRAD_CD 1
+#define LBPF_GRAD_UP2 2
 /* Storage of the distributions: FP64; or FP32 arithmetic with distributions
  * stored as offsets g_i - w_i phi and f*_i - w_i u* in FP32 or FP16 (RNE) next
  * to FP32 phi and u* fields. */
@@ -112,7 +119,7 @@ typedef struct {
   int32_t lattice;   /* LBPF_D2Q9_D2Q5, LBPF_D3Q19_D3Q7 or LBPF_D3Q15_D3Q7 */
   int32_t nx, ny, nz;/* nz = 1 in 2D; every used extent >= 3 */
   int32_t boundary;  /* LBPF_PERIODIC, LBPF_ZERO_FLUX or LBPF_MIRROR_LOW */
-  int32_t gradient;  /* LBPF_GRAD_DD or LBPF_GRAD_CD */
+  int32_t gradient;  /* LBPF_GRAD_DD, LBPF_GRAD_CD or LBPF_GRAD_UP2 */
   int32_t storage;   /* LBPF_FP64, LBPF_FP32_OFFSET or LBPF_FP16_OFFSET */
   int32_t use_ids;   /* 0: entry 0 of aniso everywhere; 1: crystal index field
                         I(x,t) selects entry I, I = 0 is isotropic (Sec. 4.3) */

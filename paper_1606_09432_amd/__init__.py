@@ -26,7 +26,7 @@ __all__ = ["Simulation", "SimConfig", "Aniso", "Seed", "workloads", "load_librar
 # C ABI mirrors (include/lb_pf.h).
 LATTICE = {"D2Q9_D2Q5": 0, "D3Q19_D3Q7": 1, "D3Q15_D3Q7": 2}
 BOUNDARY = {"periodic": 0, "zero_flux": 1, "mirror_low": 2}
-GRADIENT = {"dd": 0, "cd": 1}
+GRADIENT = {"dd": 0, "cd": 1, "up2": 2}
 STORAGE = {"fp64": 0, "fp32": 1, "fp16": 2}
 ANISO = {"iso": 0, "sectoral": 1, "cubic": 2, "cubic_hak": 3, "cubic_s": 4}
 ERR_NONFINITE = -5

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbpf.so")
-SOURCES = ["lbpf_step.hip", "lbpf_step_mirror.hip", "lbpf_aux.hip", "lbpf_api.hip"]
+SOURCES = ["lbpf_step.hip", "lbpf_step_mirror.hip", "lbpf_step_up2.hip", "lbpf_aux.hip", "lbpf_api.hip"]
 ARCH = "gfx950"  # MI355X
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -30,7 +30,7 @@ def _hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 5) -> str:
     os.makedirs(BUILD, exist_ok=True)
 
     def compile_one(src):

@@ -101,7 +101,14 @@ int validate(const lbpf_config &c) {
   }
   if (c.boundary != LBPF_PERIODIC && c.boundary != LBPF_ZERO_FLUX && c.boundary != LBPF_MIRROR_LOW)
     return fail(LBPF_ERR_ARG, "unknown boundary");
-  if (c.gradient != LBPF_GRAD_DD && c.gradient != LBPF_GRAD_CD) return fail(LBPF_ERR_ARG, "unknown gradient");
+  if (c.gradient != LBPF_GRAD_DD && c.gradient != LBPF_GRAD_CD && c.gradient != LBPF_GRAD_UP2)
+    return fail(LBPF_ERR_ARG, "unknown gradient");
+  if (c.gradient == LBPF_GRAD_UP2) {
+    if (c.use_ids || c.boundary == LBPF_MIRROR_LOW)
+      return fail(LBPF_ERR_UNSUPPORTED, "the upwind gradient runs without the index field and mirror planes");
+    if (c.nx < 4 || c.ny < 4 || (dim == 3 && c.nz < 4))
+      return fail(LBPF_ERR_ARG, "the upwind gradient needs every extent >= 4");
+  }
   if (c.storage < LBPF_FP64 || c.storage > LBPF_FP16_OFFSET) return fail(LBPF_ERR_ARG, "unknown storage");
   if (!(c.W0 > 0) || !(c.tau0 > 0) || !(c.dx > 0) || !(c.kappa > 0) || !std::isfinite(c.lambda) ||
       !std::isfinite(c.delta) || !(c.xi >= 0))
@@ -149,7 +156,7 @@ void units(const lbpf_config &c, SimHost &s) {
 // at least 16 rows each (8 in FP64).
 void default_tile(SimHost &s) {
   TileDev &t = s.tile;
-  t.ty = s.dim == 3 ? (s.storage == LBPF_FP64 ? 4 : 12) : 1;
+  t.ty = s.dim == 3 ? ((s.storage == LBPF_FP64 || s.cfg.gradient == LBPF_GRAD_UP2) ? 4 : 12) : 1;
   t.tiles_x = (s.nx + 63) / 64;
   t.tiles_y = s.dim == 3 ? (s.nyp + t.ty - 1) / t.ty : 1;
   const long long tiles = (long long)t.tiles_x * t.tiles_y;
@@ -172,6 +179,8 @@ int set_tile(SimHost &s, int ty, int chunk) {
       return fail(LBPF_ERR_UNSUPPORTED, "tile_y must be 4, 8 or 12");
     if (s.dim == 3 && ty != 4 && s.storage == LBPF_FP64)
       return fail(LBPF_ERR_UNSUPPORTED, "tile_y above 4 needs FP32 arithmetic");
+    if (s.dim == 3 && ty != 4 && s.cfg.gradient == LBPF_GRAD_UP2)
+      return fail(LBPF_ERR_UNSUPPORTED, "the upwind gradient runs on 4-row tiles");
     t.ty = ty;
   }
   if (chunk > 0) t.chunk = std::min(chunk, s.nm);
@@ -245,6 +254,7 @@ SimDev make_dev(const lbpf_handle *h, const SimHost &s, int in) {
   d.periodic = s.cfg.boundary == LBPF_PERIODIC;
   d.mirror = s.cfg.boundary == LBPF_MIRROR_LOW;
   d.grad_cd = s.cfg.gradient == LBPF_GRAD_CD;
+  d.grad_up2 = s.cfg.gradient == LBPF_GRAD_UP2;
   d.use_ids = s.cfg.use_ids != 0;
   d.n_aniso = s.cfg.n_aniso;
   d.kphi = s.kphi;
@@ -292,6 +302,8 @@ int plan_all(const lbpf_config *cfgs, int n_sims, std::vector<SimHost> &sims, si
       return fail(LBPF_ERR_UNSUPPORTED, "a batched ensemble must be 2D with one storage mode");
     if (n_sims > 1 && (cfgs[k].use_ids != 0) != (cfgs[0].use_ids != 0))
       return fail(LBPF_ERR_UNSUPPORTED, "a batched ensemble must use the index field in all or none of its configs");
+    if (n_sims > 1 && cfgs[k].gradient == LBPF_GRAD_UP2)
+      return fail(LBPF_ERR_UNSUPPORTED, "the upwind gradient runs on single simulations");
     plan(cfgs[k], sims[k], cursor);
     sims[k].aniso.assign(cfgs[k].aniso, cfgs[k].aniso + cfgs[k].n_aniso);
     sims[k].seeds.assign(cfgs[k].seeds, cfgs[k].seeds + cfgs[k].n_seeds);
@@ -695,7 +707,7 @@ int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream) {
   float best = 1e30f;
   int bty = s0.tile.ty, bch = h->batch.on ? h->batch.chunk : s0.tile.chunk;
   for (int ty : tys) {
-    if (s0.dim == 3 && ty != 4 && s0.storage == LBPF_FP64) continue;
+    if (s0.dim == 3 && ty != 4 && (s0.storage == LBPF_FP64 || s0.cfg.gradient == LBPF_GRAD_UP2)) continue;
     for (int ch : chunks) {
       if (lb_pf_set_tile(h, ty, ch)) continue;
       // warm-up of twice the trial: the trial then starts from the same

@@ -80,8 +80,10 @@ __global__ __launch_bounds__(256) void init_kernel(SimDev sd, int16_t *ids_out, 
     } else {
 #pragma unroll
       for (int i = 1; i < LP::Q; ++i) {
-        const double dd = (phn(ex<LP, DIM>(i), ey<LP, DIM>(i), em<LP, DIM>(i)) -
-                           phn(-ex<LP, DIM>(i), -ey<LP, DIM>(i), -em<LP, DIM>(i))) / 2.0;
+        const int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
+        // central, or second-order upwind (Sec. 4.2), directional derivative
+        const double dd = sd.grad_up2 ? (-phn(2 * cx, 2 * cy, 2 * cm) + 4.0 * phn(cx, cy, cm) - 3.0 * ph) / 2.0
+                                      : (phn(cx, cy, cm) - phn(-cx, -cy, -cm)) / 2.0;
         for (int a = 0; a < 3; ++a)
           if (LP::E[i][a] != 0) p[a] += (LP::W[i] * LP::E[i][a]) * dd;
       }

@@ -187,7 +187,8 @@ struct SimDev {
   const int16_t *id_in;
   int16_t *id_out;
   const AnisoDev *aniso;
-  int mirror;  // the planes through node 0 of each axis are mirror planes
+  int mirror;    // the planes through node 0 of each axis are mirror planes
+  int grad_up2;  // second-order upwind directional derivatives (Sec. 4.2)
 };
 
 __device__ __forceinline__ bool in_range(int c, int n) { return (unsigned)c < (unsigned)n; }

@@ -55,6 +55,8 @@ hipError_t launch_step_mirror(int lattice, int storage, const SimDev &sd, const 
 hipError_t launch_batch_mirror(int storage, bool ids, const SimDev *sims, const BatchItem *items, int n_items,
                                int grid, hipStream_t st);
 int batch_blocks_per_cu_mirror(int storage, bool ids);
+// The instances with the second-order upwind gradient (lbpf_step_up2.hip).
+hipError_t launch_step_up2(int lattice, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st);
 hipError_t launch_init(int lattice, int storage, const SimDev &sd, int16_t *ids_out, const InitSrc &src,
                        hipStream_t st);
 hipError_t launch_diag(int dim, int storage, const SimDev &sd, double *partials, double *result,

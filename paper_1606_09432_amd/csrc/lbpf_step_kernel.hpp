@@ -78,7 +78,10 @@ template <int DIM, int TY, class ST> constexpr int min_waves() {
 // mirror image i' of i; its coefficients are those of the ghost node at x
 // (computed from the mirrored rings: the mirror image of x', so that
 // e_i . C(x) = e_i' . C(x')).
-template <int K, int TY, class ST, bool IDS, bool BATCH, bool MIR>
+// GR = 2 takes the second-order upwind (biased) directional derivatives of
+// Sec. 4.2 through the moment of Eq. Grad_DF-Centree; the gradient then reaches
+// two nodes, so the phi ring keeps a 3-node halo and one more plane.
+template <int K, int TY, class ST, bool IDS, bool BATCH, bool MIR, int GR>
 __global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(min_waves<LatOf<K>::DIM, TY, ST>(), 8))) void
 step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const BatchItem *__restrict__ items,
             int n_items) {
@@ -92,20 +95,25 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
   constexpr int TX = 64;
   constexpr int NT = TX * TY;
   constexpr int HX = TX + 2, HY = (DIM == 3 ? TY + 2 : 1);
-  constexpr int PX = TX + 4, PY = (DIM == 3 ? TY + 4 : 1);
+  static_assert(GR == 1 || GR == 2, "gradient reach");
+  constexpr int HF = GR + 1;  // ring halo: coefficient halo + gradient reach
+  constexpr int PX = TX + 2 * HF, PY = (DIM == 3 ? TY + 2 * HF : 1);
   constexpr int NP = DIM + 3;  // A, B, C[DIM], 1/a^2
   constexpr int PLANE_P = HX * HY;
   constexpr int PLANE_F = PX * PY;
   constexpr int NHALO = PLANE_P - NT;             // halo coefficient nodes per plane
   constexpr int NLOAD = (PLANE_F + NT - 1) / NT;  // ring entries staged per thread
-  constexpr int PYO = (DIM == 3) ? 1 : 0;         // row offset of a coefficient node in the ring
+  constexpr int PYO = (DIM == 3) ? HF - 1 : 0;    // row offset of a coefficient node in the ring
+  constexpr int PXO = HF - 1;                      // column offset of a coefficient node in the ring
+  constexpr int NRP = GR + 4;                      // phi ring planes
+  constexpr int NRU = GR + 3;                      // u* and index ring planes
   constexpr int QP = LP::Q, QU = LU::Q;
   constexpr bool OFF = ST::OFF;
   static_assert(NHALO <= NT, "one halo coefficient node per thread at most");
 
-  __shared__ T phiS[5][PLANE_F];
-  __shared__ float usS[OFF ? 4 : 1][OFF ? PLANE_F : 1];
-  __shared__ int16_t idS[IDS ? 4 : 1][IDS ? PLANE_F : 1];
+  __shared__ T phiS[NRP][PLANE_F];
+  __shared__ float usS[OFF ? NRU : 1][OFF ? PLANE_F : 1];
+  __shared__ int16_t idS[IDS ? NRU : 1][IDS ? PLANE_F : 1];
   __shared__ T parS[3][NP][PLANE_P];
 
   for (int it = blockIdx.x; !BATCH || it < n_items; it += gridDim.x) {
@@ -256,11 +264,11 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       om = in1 ? -cm : (in2 ? cm : 0);
     };
 
-    // ---- ring staging: plane pm of phi^n, u*, I^n (tile + 2-node halo) --------
+    // ---- ring staging: plane pm of phi^n, u*, I^n (tile + HF-node halo) -------
     T ph_pf[NLOAD];
     float us_pf[NLOAD];
     int16_t id_pf[NLOAD];
-    // Halo coordinates beyond [-2, n + 1] (ragged last tile) are never read by a
+    // Halo coordinates beyond [-HF, n + HF - 1] (ragged last tile) are never read by a
     // node that matters: they are clamped so every load stays in the box.  The
     // FP64 form keeps the in-plane part of each ring entry (the same on every
     // plane) in registers; the offset forms recompute it, which measures faster
@@ -270,8 +278,8 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
     auto ring_xy = [&](int j, unsigned &off, bool &out) {
       const int k = min(tid + j * NT, PLANE_F - 1);
       const int px = k % PX, py = k / PX;
-      const int rx = min(max(x0 - 2 + px, -2), sd.nx + 1);
-      const int ry = (DIM == 3) ? min(max(y0 - 2 + py, -2), sd.nyp + 1) : 0;
+      const int rx = min(max(x0 - HF + px, -HF), sd.nx + HF - 1);
+      const int ry = (DIM == 3) ? min(max(y0 - HF + py, -HF), sd.nyp + HF - 1) : 0;
       const int gx = ghost(rx, sd.nx, per);
       const int gy = (DIM == 3) ? ghost(ry, sd.nyp, per) : 0;
       off = (unsigned)gy * (unsigned)pitch + (unsigned)gx;
@@ -285,7 +293,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       for (int j = 0; j < NLOAD; ++j) ring_xy(j, ring_off[j], ring_out[j]);
     }
     auto ring_fetch = [&](int pm) {
-      const int gm = ghost(pm, sd.nm, per);  // pm is always within [-2, nm + 1]
+      const int gm = ghost(pm, sd.nm, per);  // pm is always within [-HF, nm + HF - 1]
       bool mout = !per && !in_range(pm, sd.nm);
       if constexpr (MIR) {
         if (sd.mirror) mout = pm >= sd.nm;  // mirrored below 0
@@ -309,9 +317,10 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       }
     };
     // phi keeps 5 planes (B of plane m reads plane m-1 while plane m+3 is
-    // committed); u* and I^n, read in A only, keep 4
-    auto rs = [](int pm) { return (pm + 10) % 5; };
-    auto rs4 = [](int pm) { return (pm + 8) & 3; };
+    // committed); u* and I^n, read in A only, keep 4.  With GR = 2 the plane
+    // committed is m+4 and each ring keeps one plane more.
+    auto rs = [](int pm) { return GR == 1 ? (pm + 10) % 5 : (pm + 12) % 6; };
+    auto rs4 = [](int pm) { return GR == 1 ? (pm + 8) & 3 : (pm + 10) % 5; };
     auto ring_commit = [&](int pm) {
       const int slot = rs(pm), slot4 = rs4(pm);
   #pragma unroll
@@ -354,7 +363,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
     auto param_node = [&](int hx, int hy, int pm, int ps, const S(&kv)[QU], bool own_node) {
       int gx, gy, gm, mir;
       if (!node_at(hx, hy, pm, gx, gy, gm, mir)) return;
-      const int pc = (hy + PYO) * PX + (hx + 1);  // node in the ring
+      const int pc = (hy + PYO) * PX + (hx + PXO);  // node in the ring
       const int sl0 = rs(pm);
       const T phc = phiS[sl0][pc];
       // gradient of phi^n, lattice units
@@ -374,7 +383,12 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
         for (int i = 1; i < QP; ++i) {
           if (LP::OPP[i] < i) continue;
           const int o = ey<LP, DIM>(i) * PX + ex<LP, DIM>(i);
-          const T dd = phiS[rs(pm + em<LP, DIM>(i))][pc + o] - phiS[rs(pm - em<LP, DIM>(i))][pc - o];
+          T dd = phiS[rs(pm + em<LP, DIM>(i))][pc + o] - phiS[rs(pm - em<LP, DIM>(i))][pc - o];
+          if constexpr (GR == 2) {
+            // second-order upwind pair: 2 [f(x+e) - f(x-e)] - [f(x+2e) - f(x-2e)] / 2
+            const T d2 = phiS[rs(pm + 2 * em<LP, DIM>(i))][pc + 2 * o] - phiS[rs(pm - 2 * em<LP, DIM>(i))][pc - 2 * o];
+            dd = T(2) * dd - T(0.5) * d2;
+          }
           if (LP::E[i][0] != 0) p0 += (T(LP::W[i]) * T(LP::E[i][0])) * dd;
           if (LP::E[i][1] != 0) p1 += (T(LP::W[i]) * T(LP::E[i][1])) * dd;
           if (LP::E[i][2] != 0) p2 += (T(LP::W[i]) * T(LP::E[i][2])) * dd;
@@ -470,7 +484,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
     const int gy_o = y0 + ty;
     const bool own = in_range(gx_o, sd.nx) && (DIM == 2 || in_range(gy_o, sd.nyp));
     const int nodeo = hy_o * HX + hx_o;
-    const int pco = (hy_o + PYO) * PX + (hx_o + 1);
+    const int pco = (hy_o + PYO) * PX + (hx_o + PXO);
 
     int sp = 0, sc = 1, sn = 2;  // coefficient slots of planes m-1, m, m+1
 
@@ -618,9 +632,9 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
     auto walls_at = [&](int m) { return !per && (xy_walls || m == 0 || m == sd.nm - 1); };
 
     // ---- warm-up ----------------------------------------------------------------
-    // ring planes m0-2 .. m0+1; coefficients of planes m0-1 and m0 (gathers
-    // loaded on the spot); then ring plane m0+2 and the gathers of plane m0+1
-    for (int pm = m0 - 2; pm <= m0 + 1; ++pm) {
+    // ring planes m0-1-GR .. m0+GR; coefficients of planes m0-1 and m0 (gathers
+    // loaded on the spot); then ring plane m0+GR+1 and the gathers of plane m0+1
+    for (int pm = m0 - 1 - GR; pm <= m0 + GR; ++pm) {
       ring_fetch(pm);
       ring_commit(pm);
     }
@@ -633,8 +647,8 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       if (has_h) param_node(hx_h, hy_h, pm, ps, kv_h_c, false);
     }
     __syncthreads();
-    ring_fetch(m0 + 2);
-    ring_commit(m0 + 2);
+    ring_fetch(m0 + GR + 1);
+    ring_commit(m0 + GR + 1);
     gather_fetch(hx_o, hy_o, m0 + 1, kv_o_c);
     if (has_h) gather_fetch(hx_h, hy_h, m0 + 1, kv_h_c);
   #pragma unroll
@@ -646,8 +660,8 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
 
     for (int m = m0; m < m1; ++m) {
       // loads for the next iterations: ring plane m+3, gathers of plane m+2
-      const bool more_ring = m + 3 <= m1 + 1;
-      if (more_ring) ring_fetch(m + 3);
+      const bool more_ring = m + GR + 2 <= m1 + GR;
+      if (more_ring) ring_fetch(m + GR + 2);
       if (m + 2 <= m1) {
         gather_fetch(hx_o, hy_o, m + 2, kv_o_n);
         if (has_h) gather_fetch(hx_h, hy_h, m + 2, kv_h_n);
@@ -658,7 +672,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       __syncthreads();
       // B: plane m
       if (own) output(m, walls_at(m));
-      if (more_ring) ring_commit(m + 3);
+      if (more_ring) ring_commit(m + GR + 2);
       __syncthreads();
       // rotate the coefficient ring, the own-column state and the prefetches
       const int t = sp;
@@ -681,13 +695,28 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
 
 
 // ---- launchers, instantiated once per value of MIR (one source file each) ----
-template <int K, int TY, class ST, bool IDS, bool MIR>
+template <int K, int TY, class ST, bool IDS, bool MIR, int GR = 1>
 static hipError_t launch_step_t(const SimDev &sd, const TileDev &tc, hipStream_t st) {
   const int nblocks = tc.tiles_x * tc.tiles_y * tc.nchunks;
   dim3 block(64, LatOf<K>::DIM == 3 ? TY : 1);
-  hipLaunchKernelGGL((step_kernel<K, TY, ST, IDS, false, MIR>), dim3(nblocks), block, 0, st, sd, tc, nullptr,
+  hipLaunchKernelGGL((step_kernel<K, TY, ST, IDS, false, MIR, GR>), dim3(nblocks), block, 0, st, sd, tc, nullptr,
                      nullptr, 0);
   return hipGetLastError();
+}
+
+// The second-order upwind gradient (GR = 2): one tile height (4 rows in 3D),
+// no index field, no mirror planes, single simulations.
+template <int K, class ST> static hipError_t launch_step_up2_st(const SimDev &sd, const TileDev &tc, hipStream_t st) {
+  if (LatOf<K>::DIM == 3 && tc.ty != 4) return hipErrorInvalidValue;
+  return launch_step_t<K, LatOf<K>::DIM == 3 ? 4 : 1, ST, false, false, 2>(sd, tc, st);
+}
+template <int K> static hipError_t launch_step_up2_k(int storage, const SimDev &sd, const TileDev &tc, hipStream_t st) {
+  switch (storage) {
+    case 0: return launch_step_up2_st<K, StF64>(sd, tc, st);
+    case 1: return launch_step_up2_st<K, StF32>(sd, tc, st);
+    case 2: return launch_step_up2_st<K, StF16>(sd, tc, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int K, class ST, bool IDS, bool MIR>
@@ -735,7 +764,7 @@ static hipError_t launch_step_m(int lattice, int storage, const SimDev &sd, cons
 
 template <class ST, bool IDS, bool MIR>
 static hipError_t launch_batch_t(const SimDev *sims, const BatchItem *items, int n_items, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((step_kernel<0, 1, ST, IDS, true, MIR>), dim3(grid), dim3(64), 0, st, SimDev{}, TileDev{}, sims,
+  hipLaunchKernelGGL((step_kernel<0, 1, ST, IDS, true, MIR, 1>), dim3(grid), dim3(64), 0, st, SimDev{}, TileDev{}, sims,
                      items, n_items);
   return hipGetLastError();
 }
@@ -757,7 +786,7 @@ static hipError_t launch_batch_m(int storage, bool ids, const SimDev *sims, cons
 
 template <class ST, bool IDS, bool MIR> static int batch_occupancy_t() {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<0, 1, ST, IDS, true, MIR>, 64, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, step_kernel<0, 1, ST, IDS, true, MIR, 1>, 64, 0) != hipSuccess)
     return 0;
   return nb;
 }

@@ -97,6 +97,27 @@ def test_boundary_values(lib):
     assert "boundary" in lib.lb_pf_last_error().decode()
 
 
+def test_upwind_gradient_rules(lib):
+    """LBPF_GRAD_UP2 (2) is valid for single simulations without the index
+    field or mirror planes, with every extent >= 4; 3 is no gradient."""
+    keep = []
+    b = C.c_size_t()
+
+    def rc(cfg, n=1):
+        arr = (lb.LbpfConfig * n)(*[lb._to_struct(cfg, keep) for _ in range(n)])
+        return lib.lb_pf_workspace_bytes(arr, n, C.byref(b))
+
+    base = W.c0(n=32).replace(gradient="up2")
+    assert rc(base) == 0
+    assert rc(W.small_3d(n=8).replace(gradient="up2")) == 0
+    assert rc(base.replace(nx=3)) == -1
+    assert rc(base.replace(boundary="mirror_low")) == -6
+    assert rc(base, n=2) == -6
+    s = lb._to_struct(base, keep)
+    s.gradient = 3
+    assert lib.lb_pf_workspace_bytes(C.byref(s), 1, C.byref(b)) == -1
+
+
 def test_init_rejects_missing_workspace(lib):
     keep = []
     s = lb._to_struct(W.c0(n=32), keep)
