@@ -4,7 +4,7 @@
  * The library advances the pure-substance phase-field model of Younsi &
  * Cartalade (arXiv:1606.09432), Sec. 2 (Eqs. PhaseField_KarmaRappel and
  * Temp_Ramirez), with the lattice Boltzmann schemes of Sec. 3:
- *   - phi on D2Q9 (2D) or D3Q19 (3D) with the nonlocal a_s^2 scheme of
+ *   - phi on D2Q9 (2D), D3Q19 or D3Q15 (3D) with the nonlocal a_s^2 scheme of
  *     Eq. LBE_Eq_Phase, the equilibrium of Eq. Feq_Phase, the relaxation rate of
  *     Eq. LBE_RelaxationTime and the source of Eq. LBE_SourceTerm;
  *   - u on D2Q5 (2D) or D3Q7 (3D) with the BGK scheme of Eq. LBE_Eq_Temp, the
@@ -12,11 +12,13 @@
  *     (Eq. Source_Tempr with the explicit Euler derivative of Sec. 3.1);
  *   - the anisotropy a_s(n) and its flux N (Eq. TermesAnisotropes) built from
  *     directional derivatives along every lattice vector (Sec. 4.2, Eqs.
- *     Def_DeriveeDirectionnelle and Grad_DF-Centree), or from central
- *     differences (the comparison variant of Sec. 4.2);
+ *     Def_DeriveeDirectionnelle and Grad_DF-Centree), from central
+ *     differences (the comparison variant of Sec. 4.2), or from the
+ *     second-order upwind directional derivatives of Sec. 4.2;
  *   - per-crystal anisotropy through a crystal index field (Sec. 4.3);
- *   - zero-flux walls by bounce-back (Sec. 3.3, Eq. Bounce-Back) or periodic
- *     boundaries.
+ *   - zero-flux walls by bounce-back (Sec. 3.3, Eq. Bounce-Back), periodic
+ *     boundaries, or mirror planes through node 0 (one octant of a symmetric
+ *     domain, Sec. 5).
  *
  * Conventions
  *   - Every function returns 0 (LBPF_OK) or a negative status; after a failure
