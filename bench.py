@@ -565,16 +565,33 @@ def main():
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write profiles/hbm_traffic.json from four --pmc runs")
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--command", default="", help="the profiling command, recorded in the summary")
+    ap.add_argument("--command", default="", help="the profiling command recorded in the summary "
+                    "(default: the commands these summaries are made with)")
     ap.add_argument("--bench-json", default=None)
     ap.add_argument("--out", default=None)
     args = ap.parse_args()
     if args.summarize_trace:
-        text = summarize_trace(args.summarize_trace, args.command, args.bench_json)
+        cmd = args.command or "\n".join([
+            f"rocprofv3 --kernel-trace --stats -d {args.summarize_trace} -o bench -- python bench.py"
+            + (f" > {args.bench_json}" if args.bench_json else ""),
+            f"python bench.py --summarize-trace {args.summarize_trace}"
+            + (f" --bench-json {args.bench_json}" if args.bench_json else "")
+            + (f" --out {args.out}" if args.out else "")])
+        text = summarize_trace(args.summarize_trace, cmd, args.bench_json)
         open(args.out, "w").write(text) if args.out else print(text)
         return
     if args.summarize_traffic:
-        res, md = summarize_traffic(*args.summarize_traffic, args.copy_mib * (1 << 20), args.command)
+        fd, wd, cfd, cwd = args.summarize_traffic
+        run = "python bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-batched"
+        cal = f"python bench.py --calibrate-copy {args.copy_mib}"
+        cmd = args.command or "\n".join([
+            f"rocprofv3 --pmc FETCH_SIZE -d {fd} -o bench -- {run}",
+            f"rocprofv3 --pmc WRITE_SIZE -d {wd} -o bench -- {run}",
+            f"rocprofv3 --pmc FETCH_SIZE -d {cfd} -o copy -- {cal}",
+            f"rocprofv3 --pmc WRITE_SIZE -d {cwd} -o copy -- {cal}",
+            f"python bench.py --summarize-traffic {fd} {wd} {cfd} {cwd} --copy-mib {args.copy_mib}"
+            + (f" --out {args.out}" if args.out else "")])
+        res, md = summarize_traffic(*args.summarize_traffic, args.copy_mib * (1 << 20), cmd)
         json.dump(res, open(TRAFFIC_FILE, "w"), indent=1)
         open(args.out, "w").write(md) if args.out else print(md)
         return

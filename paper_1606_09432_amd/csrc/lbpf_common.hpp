@@ -133,24 +133,34 @@ struct StF64 {
   using S = double;  // stored distribution
   using P = double;  // stored phi
   static constexpr bool OFF = false;
+  static constexpr bool COMP = false;
   static __device__ __forceinline__ T ld(const S *p) { return *p; }
   static __device__ __forceinline__ void st(S *p, T v) { *p = v; }
+  static __device__ __forceinline__ S enc(T v) { return v; }
+  static __device__ __forceinline__ T dec(S s) { return s; }
 };
 struct StF32 {
   using T = float;
   using S = float;
   using P = float;
   static constexpr bool OFF = true;
+  static constexpr bool COMP = false;
   static __device__ __forceinline__ T ld(const S *p) { return *p; }
   static __device__ __forceinline__ void st(S *p, T v) { *p = v; }
+  static __device__ __forceinline__ S enc(T v) { return v; }
+  static __device__ __forceinline__ T dec(S s) { return s; }
 };
 struct StF16 {
   using T = float;
   using S = __half;
   using P = float;
   static constexpr bool OFF = true;
+  // the rest offset balances the rounded others (FP16 rounding is coarse)
+  static constexpr bool COMP = true;
   static __device__ __forceinline__ T ld(const S *p) { return __half2float(*p); }
   static __device__ __forceinline__ void st(S *p, T v) { *p = __float2half_rn(v); }
+  static __device__ __forceinline__ S enc(T v) { return __float2half_rn(v); }
+  static __device__ __forceinline__ T dec(S s) { return __half2float(s); }
 };
 
 // Anisotropy entry as the kernels see it (cos/sin of q phi0 precomputed on the host).

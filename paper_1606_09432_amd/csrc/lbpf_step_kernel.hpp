@@ -599,10 +599,24 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
   #pragma unroll
       for (int i = 0; i < QP; ++i) sum += d[i];
       const T phn = OFF ? phy + sum : sum;
+      if constexpr (OFF) {
+        // the offsets of a node sum to zero. With COMP the rest offset is stored
+        // as minus the sum of the others as rounded, so their rounding errors
+        // cancel in the next step's phi; the rest offset itself stays near
+        // zero, so its own rounding is small
+        T rsum = T(0);
   #pragma unroll
-      for (int i = 0; i < QP; ++i) {
-        const T v = OFF ? d[i] - T(LP::W[i]) * sum : d[i];
-        ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(gofield(i)) + iyb), v);
+        for (int i = 1; i < QP; ++i) {
+          const S q = ST::enc(d[i] - T(LP::W[i]) * sum);
+          *reinterpret_cast<S *>(reinterpret_cast<char *>(gofield(i)) + iyb) = q;
+          rsum += ST::dec(q);
+        }
+        ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(gofield(0)) + iyb),
+               ST::COMP ? -rsum : d[0] - T(LP::W[0]) * sum);
+      } else {
+  #pragma unroll
+        for (int i = 0; i < QP; ++i)
+          ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(gofield(i)) + iyb), d[i]);
       }
       stb(Phout, iy * (unsigned)sizeof(PT), (PT)phn);
 
@@ -612,9 +626,15 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       if constexpr (OFF) {
         const T Sm = u_cur - us_cur;  // sum of the decoded offsets
         const T keep = T(1) - om_u;
+        T rsum = T(0);  // as for g: the rest population balances the rounded others
   #pragma unroll
-        for (int i = 0; i < QU; ++i)
-          ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(i)) + iyb), keep * (fd_cur[i] - T(LU::W[i]) * Sm));
+        for (int i = 1; i < QU; ++i) {
+          const S q = ST::enc(keep * (fd_cur[i] - T(LU::W[i]) * Sm));
+          *reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(i)) + iyb) = q;
+          rsum += ST::dec(q);
+        }
+        ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(0)) + iyb),
+               ST::COMP ? -rsum : keep * (fd_cur[0] - T(LU::W[0]) * Sm));
         stb(sd.us_out, iy * 4u, float(u_cur + half_dphi));
       } else {
   #pragma unroll
