@@ -535,6 +535,43 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, 
     return res, "\n".join(md) + "\n"
 
 
+SQ_PASSES = (("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR", "SQ_INSTS_SALU",
+              "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES"),
+             ("SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_ANY",
+              "SQ_ACTIVE_INST_ANY", "SQ_INSTS_SMEM", "SQ_ACTIVE_INST_SCA"))
+
+
+def summarize_sq(d1, d2, command):
+    """Instruction mix and wave-time split of the 512^3 step kernels from two
+    --pmc passes of SQ counters (the counts are whole-chip sums per dispatch)."""
+    a, b = _pmc(d1), _pmc(d2)
+    nodes = 512 ** 3
+    md = ["# Instruction mix of the step kernel (rocprofv3 --pmc, SQ counters)", "",
+          "Commands (from the repository root):", "", "```", command, "```", "",
+          "Instructions are wave instructions x 64 lanes / 512^3 nodes, i.e. per node and step, halo work "
+          "included. The time split divides each wave's active or waiting time by its lifetime "
+          "(SQ_ACTIVE_INST_* and SQ_WAIT_ANY over SQ_WAVE_CYCLES).", "",
+          "| kernel | waves | VALU/node | SALU/node | LDS/node | VMEM rd/node | VMEM wr/node | VALU active | "
+          "SALU active | LDS active | waiting | LDS bank conflicts/LDS instr |",
+          "|---|---|---|---|---|---|---|---|---|---|---|---|"]
+    for k in sorted(a):
+        if not k.startswith("step_kernel<1,") and not k.startswith("step_kernel<2,"):
+            continue
+        v = dict(a[k])
+        v.update(b.get(k, {}))
+        if any(c not in v for c in SQ_PASSES[0] + SQ_PASSES[1]):
+            continue
+        per = lambda c: v[c] * 64 / nodes  # noqa: E731
+        cyc = v["SQ_WAVE_CYCLES"]
+        md.append(f"| `{k}` | {v['SQ_WAVES']:.0f} | {per('SQ_INSTS_VALU'):.0f} | {per('SQ_INSTS_SALU'):.0f} | "
+                  f"{per('SQ_INSTS_LDS'):.0f} | {per('SQ_INSTS_VMEM_RD'):.1f} | {per('SQ_INSTS_VMEM_WR'):.1f} | "
+                  f"{v['SQ_ACTIVE_INST_VALU'] / cyc:.2f} | {v['SQ_ACTIVE_INST_SCA'] / cyc:.2f} | "
+                  f"{v['SQ_ACTIVE_INST_LDS'] / cyc:.2f} | {v['SQ_WAIT_ANY'] / cyc:.2f} | "
+                  f"{v['SQ_LDS_BANK_CONFLICT'] / max(v['SQ_INSTS_LDS'], 1):.3f} |")
+    md += ["", f"Kernel source hash: {kernel_sha()} (comments and blank lines excluded)."]
+    return "\n".join(md) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -564,6 +601,8 @@ def main():
     ap.add_argument("--summarize-trace", metavar="DIR", help="write a markdown summary of a --kernel-trace run")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="write profiles/hbm_traffic.json from four --pmc runs")
+    ap.add_argument("--summarize-sq", nargs=2, metavar=("PASS1", "PASS2"),
+                    help="write a markdown summary of the two SQ counter --pmc runs")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--command", default="", help="the profiling command recorded in the summary "
                     "(default: the commands these summaries are made with)")
@@ -578,6 +617,14 @@ def main():
             + (f" --bench-json {args.bench_json}" if args.bench_json else "")
             + (f" --out {args.out}" if args.out else "")])
         text = summarize_trace(args.summarize_trace, cmd, args.bench_json)
+        open(args.out, "w").write(text) if args.out else print(text)
+        return
+    if args.summarize_sq:
+        run = "python bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-batched"
+        cmd = args.command or "\n".join(
+            [f"rocprofv3 --pmc {' '.join(p)} -d {d} -o bench -- {run}" for p, d in zip(SQ_PASSES, args.summarize_sq)]
+            + [f"python bench.py --summarize-sq {' '.join(args.summarize_sq)}" + (f" --out {args.out}" if args.out else "")])
+        text = summarize_sq(*args.summarize_sq, cmd)
         open(args.out, "w").write(text) if args.out else print(text)
         return
     if args.summarize_traffic:
