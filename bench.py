@@ -572,6 +572,26 @@ def summarize_sq(d1, d2, command):
     return "\n".join(md) + "\n"
 
 
+def summarize_counters(dirs, command, title):
+    """Per-dispatch values and per-node figures of every counter in the given
+    --pmc runs, for the 512^3 step kernels of the 3D workload."""
+    vals = {}
+    for d in dirs:
+        for k, c in _pmc(d).items():
+            if k.startswith("step_kernel<1,") or k.startswith("step_kernel<2,"):
+                vals.setdefault(k, {}).update(c)
+    names = sorted({c for v in vals.values() for c in v})
+    nodes = 512 ** 3
+    md = [f"# {title}", "", "Commands (from the repository root):", "", "```", command, "```", "",
+          "Each cell: counter value per dispatch (whole chip) / the same per node of the 512^3 grid.", "",
+          "| kernel | " + " | ".join(names) + " |", "|---|" + "---|" * len(names)]
+    for k in sorted(vals):
+        md.append(f"| `{k}` | " + " | ".join(
+            f"{vals[k][c]:.4g} / {vals[k][c] / nodes:.3f}" if c in vals[k] else "—" for c in names) + " |")
+    md += ["", f"Kernel source hash: {kernel_sha()} (comments and blank lines excluded)."]
+    return "\n".join(md) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -603,6 +623,9 @@ def main():
                     help="write profiles/hbm_traffic.json from four --pmc runs")
     ap.add_argument("--summarize-sq", nargs=2, metavar=("PASS1", "PASS2"),
                     help="write a markdown summary of the two SQ counter --pmc runs")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                    help="write a markdown table of the counters of one or more --pmc runs")
+    ap.add_argument("--title", default="Counters of the step kernel (rocprofv3 --pmc)")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--command", default="", help="the profiling command recorded in the summary "
                     "(default: the commands these summaries are made with)")
@@ -617,6 +640,12 @@ def main():
             + (f" --bench-json {args.bench_json}" if args.bench_json else "")
             + (f" --out {args.out}" if args.out else "")])
         text = summarize_trace(args.summarize_trace, cmd, args.bench_json)
+        open(args.out, "w").write(text) if args.out else print(text)
+        return
+    if args.summarize_counters:
+        if not args.command:
+            raise SystemExit("--summarize-counters needs --command (the rocprofv3 runs that made the directories)")
+        text = summarize_counters(args.summarize_counters, args.command, args.title)
         open(args.out, "w").write(text) if args.out else print(text)
         return
     if args.summarize_sq:
