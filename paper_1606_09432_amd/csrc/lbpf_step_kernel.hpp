@@ -37,6 +37,9 @@
 //   h*_i(x) = A h_i(x) + w_i (Q s + e_i . C),  A = 1 - w,  C = -w (Dphi/e^2) N
 //   d_i     = h_i(y) + [w_i (phi(x) - phi(y)) + h*_i(x) - h_i(y)] / a^2(x)
 //   phi^{n+1}(y) = phi^n(y) + sum_i d_i,   h_i^{n+1}(y) = d_i - w_i sum_j d_j.
+// In FP16 the rest offset h_0 is stored as minus the sum of the other offsets
+// as rounded (likewise k_0), so the stored offsets of a node sum to zero up to
+// the rounding of h_0, which stays near zero.
 #pragma once
 
 #include <type_traits>
