@@ -125,6 +125,19 @@ template <class L, int DIM> __device__ __forceinline__ int mirror_sel(int i, int
   return r;
 }
 
+// Stores of the step's outputs carry the non-temporal hint: no launch reads
+// what it writes, and keeping the written lines out of the way in L2 leaves it
+// to the rows that the neighbouring planes read again.
+template <class E> __device__ __forceinline__ void nt_store(E *p, E v) {
+  if constexpr (sizeof(E) == 2) {
+    unsigned short b;
+    __builtin_memcpy(&b, &v, 2);
+    __builtin_nontemporal_store(b, reinterpret_cast<unsigned short *>(p));
+  } else {
+    __builtin_nontemporal_store(v, p);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Storage: FP64 distributions, or FP32 arithmetic on offsets stored in FP32/FP16.
 // ---------------------------------------------------------------------------
@@ -135,7 +148,7 @@ struct StF64 {
   static constexpr bool OFF = false;
   static constexpr bool COMP = false;
   static __device__ __forceinline__ T ld(const S *p) { return *p; }
-  static __device__ __forceinline__ void st(S *p, T v) { *p = v; }
+  static __device__ __forceinline__ void st(S *p, T v) { nt_store(p, S(v)); }
   static __device__ __forceinline__ S enc(T v) { return v; }
   static __device__ __forceinline__ T dec(S s) { return s; }
 };
@@ -146,7 +159,7 @@ struct StF32 {
   static constexpr bool OFF = true;
   static constexpr bool COMP = false;
   static __device__ __forceinline__ T ld(const S *p) { return *p; }
-  static __device__ __forceinline__ void st(S *p, T v) { *p = v; }
+  static __device__ __forceinline__ void st(S *p, T v) { nt_store(p, S(v)); }
   static __device__ __forceinline__ S enc(T v) { return v; }
   static __device__ __forceinline__ T dec(S s) { return s; }
 };
@@ -158,7 +171,7 @@ struct StF16 {
   // the rest offset balances the rounded others (FP16 rounding is coarse)
   static constexpr bool COMP = true;
   static __device__ __forceinline__ T ld(const S *p) { return __half2float(*p); }
-  static __device__ __forceinline__ void st(S *p, T v) { *p = __float2half_rn(v); }
+  static __device__ __forceinline__ void st(S *p, T v) { nt_store(p, __float2half_rn(v)); }
   static __device__ __forceinline__ S enc(T v) { return __float2half_rn(v); }
   static __device__ __forceinline__ T dec(S s) { return __half2float(s); }
 };

@@ -63,7 +63,7 @@ template <class E> __device__ __forceinline__ E ldb(const E *base, unsigned boff
   return *reinterpret_cast<const E *>(reinterpret_cast<const char *>(base) + boff);
 }
 template <class E> __device__ __forceinline__ void stb(E *base, unsigned boff, E v) {
-  *reinterpret_cast<E *>(reinterpret_cast<char *>(base) + boff) = v;
+  nt_store(reinterpret_cast<E *>(reinterpret_cast<char *>(base) + boff), v);
 }
 
 // Minimum waves per SIMD the register allocator must leave room for.
@@ -611,7 +611,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
   #pragma unroll
         for (int i = 1; i < QP; ++i) {
           const S q = ST::enc(d[i] - T(LP::W[i]) * sum);
-          *reinterpret_cast<S *>(reinterpret_cast<char *>(gofield(i)) + iyb) = q;
+          nt_store(reinterpret_cast<S *>(reinterpret_cast<char *>(gofield(i)) + iyb), q);
           rsum += ST::dec(q);
         }
         ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(gofield(0)) + iyb),
@@ -633,7 +633,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
   #pragma unroll
         for (int i = 1; i < QU; ++i) {
           const S q = ST::enc(keep * (fd_cur[i] - T(LU::W[i]) * Sm));
-          *reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(i)) + iyb) = q;
+          nt_store(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(i)) + iyb), q);
           rsum += ST::dec(q);
         }
         ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(0)) + iyb),
