@@ -62,6 +62,25 @@ __device__ __forceinline__ int xcd_remap(int b, int nb) {
 template <class E> __device__ __forceinline__ E ldb(const E *base, unsigned boff) {
   return *reinterpret_cast<const E *>(reinterpret_cast<const char *>(base) + boff);
 }
+// f(integral_constant<int, I>) for I = I0 .. N-1, unrolled at compile time.
+template <int I, int N, class F> __device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+// Load with the non-temporal hint, for the last read of a line's data.
+template <class E> __device__ __forceinline__ E ldb_nt(const E *base, unsigned boff) {
+  const E *p = reinterpret_cast<const E *>(reinterpret_cast<const char *>(base) + boff);
+  if constexpr (sizeof(E) == 2) {
+    const unsigned short b = __builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p));
+    E v;
+    __builtin_memcpy(&v, &b, 2);
+    return v;
+  } else {
+    return __builtin_nontemporal_load(p);
+  }
+}
 template <class E> __device__ __forceinline__ void stb(E *base, unsigned boff, E v) {
   nt_store(reinterpret_cast<E *>(reinterpret_cast<char *>(base) + boff), v);
 }
@@ -499,19 +518,33 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       bool unk[QP];
       // one batch of loads: g_i(y) and g_i(y - e_i)
       const bool fast = xy_in1 && m >= 1 && m + 1 < sd.nm;
+      // Each population is read twice, as the own value of its node and as the
+      // upstream value of the node downstream. The second of the two reads
+      // carries the non-temporal hint, so that L2 keeps the lines still to be
+      // read again: for e_m = +1 the upstream row (plane m - 1, read as its own
+      // one plane earlier), for e_m = -1 the own row (read as upstream one
+      // plane earlier). The choice is made at compile time; a hinted and a
+      // plain load of one address would be merged into a plain one.
       auto load_fast = [&]() {
-  #pragma unroll
-        for (int i = 0; i < QP; ++i) {
+        static_for<0, QP>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
           unk[i] = false;
-          gy_r[i] = ldb(gfield(i), iyb);
-          gx_r[i] = ldb(gfield(i), iyb + boff_of(ex<LP, DIM>(i), ey<LP, DIM>(i), em<LP, DIM>(i), sizeof(S)));
-        }
+          const unsigned bx = iyb + boff_of(ex<LP, DIM>(i), ey<LP, DIM>(i), em<LP, DIM>(i), sizeof(S));
+          if constexpr (em<LP, DIM>(i) == -1)
+            gy_r[i] = ldb_nt(gfield(i), iyb);
+          else
+            gy_r[i] = ldb(gfield(i), iyb);
+          if constexpr (em<LP, DIM>(i) == 1)
+            gx_r[i] = ldb_nt(gfield(i), bx);
+          else
+            gx_r[i] = ldb(gfield(i), bx);
+        });
       };
       auto load_generic = [&](auto flip) {
         constexpr bool FLIP = decltype(flip)::value;
-  #pragma unroll
-        for (int i = 0; i < QP; ++i) {
-          const int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
+        static_for<0, QP>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          constexpr int cx = ex<LP, DIM>(i), cy = ey<LP, DIM>(i), cm = em<LP, DIM>(i);
           int sx = gx_o - cx, sy = gy_o - cy, sm = m - cm;
           int fl = 0;  // mirrored axes of the source (bit 0 x, 1 yp, 2 m)
           if constexpr (FLIP) {
@@ -532,13 +565,19 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
             unk[i] = !(in_range(sx, sd.nx) && (DIM == 2 || in_range(sy, sd.nyp)) && in_range(sm, sd.nm));
           }
           const unsigned isrc = unk[i] ? iy : lin(sd, sx, sy, sm);
-          gy_r[i] = ldb(gfield(i), iyb);
+          if constexpr (cm == -1)
+            gy_r[i] = ldb_nt(gfield(i), iyb);
+          else
+            gy_r[i] = ldb(gfield(i), iyb);
           if constexpr (FLIP) {
             gx_r[i] = ldb(gfield(mirror_sel<LP, DIM>(i, fl)), isrc * (unsigned)sizeof(S));
           } else {
-            gx_r[i] = ldb(gfield(i), isrc * (unsigned)sizeof(S));
+            if constexpr (cm == 1)
+              gx_r[i] = ldb_nt(gfield(i), isrc * (unsigned)sizeof(S));
+            else
+              gx_r[i] = ldb(gfield(i), isrc * (unsigned)sizeof(S));
           }
-        }
+        });
       };
       T phy;
       T d[QP];
