@@ -91,7 +91,9 @@ extern "C" {
 #define LBPF_GRAD_UP2 2
 /* Storage of the distributions: FP64; or FP32 arithmetic with distributions
  * stored as offsets g_i - w_i phi and f*_i - w_i u* in FP32 or FP16 (RNE) next
- * to FP32 phi and u* fields. */
+ * to FP32 phi and u* fields. In FP16 the rest offset (i = 0) is stored as minus
+ * the sum of the other offsets of the node as rounded, so that the offsets of
+ * a node sum to zero up to the rounding of that near-zero value. */
 #define LBPF_FP64 0
 #define LBPF_FP32_OFFSET 1
 #define LBPF_FP16_OFFSET 2
