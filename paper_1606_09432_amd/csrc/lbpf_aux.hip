@@ -116,13 +116,22 @@ __global__ __launch_bounds__(256) void init_kernel(SimDev sd, int16_t *ids_out, 
     const AnisoDev *A = sd.use_ids ? (id > 0 ? sd.aniso + id : nullptr) : sd.aniso;
     double a, Nv[3];
     flux<double>(A, p[0], p[1], p[2], a, Nv[0], Nv[1], Nv[2]);
-    // g = g^(0)(phi, N), Eq. Feq_Phase (lattice units)
+    // g = g^(0)(phi, N), Eq. Feq_Phase (lattice units). The offsets sum to
+    // zero; as in the step, FP16 stores the rest offset (i = 0, written last)
+    // as minus the sum of the others as rounded.
+    typename ST::T rsum = 0;
 #pragma unroll
-    for (int i = 0; i < LP::Q; ++i) {
+    for (int i = LP::Q - 1; i >= 0; --i) {
       const double eN = (LP::E[i][0] * Nv[0] + LP::E[i][1] * Nv[1]) + LP::E[i][2] * Nv[2];
       const double geq = LP::W[i] * (ph - sd.kphi * eN);
-      ST::st(G + (long long)i * sd.fstride + idx,
-             typename ST::T(ST::OFF ? -LP::W[i] * sd.kphi * eN : geq));
+      typename ST::T v = typename ST::T(ST::OFF ? -LP::W[i] * sd.kphi * eN : geq);
+      if constexpr (ST::COMP) {
+        if (i == 0)
+          v = -rsum;
+        else
+          rsum += ST::dec(ST::enc(v));
+      }
+      ST::st(G + (long long)i * sd.fstride + idx, v);
     }
     Ph[idx] = (typename ST::P)ph;
     // heat populations stored post-collision at the source, so that the first
