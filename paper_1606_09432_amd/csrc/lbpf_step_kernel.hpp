@@ -549,8 +549,11 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
           int fl = 0;  // mirrored axes of the source (bit 0 x, 1 yp, 2 m)
           if constexpr (FLIP) {
             // only a component +1 can cross a plane through node 0: the
-            // flags of the other components are zero at compile time
-            const bool fx = cx == 1 && gx_o == 0, fy = DIM == 3 && cy == 1 && gy_o == 0, fm = cm == 1 && m == 0;
+            // flags of the other components are zero at compile time; a
+            // simulation without mirror planes never sets them
+            const bool mir = sd.mirror;
+            const bool fx = mir && cx == 1 && gx_o == 0, fy = mir && DIM == 3 && cy == 1 && gy_o == 0,
+                       fm = mir && cm == 1 && m == 0;
             fl = (fx ? 1 : 0) | (fy ? 2 : 0) | (fm ? 4 : 0);
             if (fx) sx = 1;
             if (fy) sy = 1;
@@ -605,15 +608,15 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
         }
       };
       if constexpr (MIR) {
-        // only tiles on a mirror plane load mirrored populations; the pulls
-        // take the ghost coefficient nodes beyond the plane as they are
-        const bool low = sd.mirror && (x0 == 0 || (DIM == 3 && y0 == 0) || m == 0);
+        // the generic loads take a mirrored population where the source lies
+        // beyond a mirror plane (the flags are zero elsewhere, and for members
+        // of an ensemble without mirror planes); the pulls take the ghost
+        // coefficient nodes beyond the plane as they are.  One generic path
+        // instead of two leaves the mirror instances fewer registers.
         if (fast)
           load_fast();
-        else if (low)
-          load_generic(std::true_type{});
         else
-          load_generic(std::false_type{});
+          load_generic(std::true_type{});
         phy = phiS[rs(m)][pco];
         pull();
       } else {
