@@ -701,9 +701,17 @@ int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream) {
   const SimHost &s0 = h->sims[0];
   std::vector<int> tys = s0.dim == 3 ? std::vector<int>{4, 8, 12} : std::vector<int>{1};
   std::vector<int> chunks = s0.dim == 3 ? std::vector<int>{16, 32, 64, 128} : std::vector<int>{8, 16, 32, 64};
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  // the two timing events, destroyed on every return
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) hipEventDestroy(x);
+    }
+  } ev;
+  HIPCHK(hipEventCreate(&ev.e[0]));
+  HIPCHK(hipEventCreate(&ev.e[1]));
+  hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
   float best = 1e30f;
   int bty = s0.tile.ty, bch = h->batch.on ? h->batch.chunk : s0.tile.chunk;
   for (int ty : tys) {
@@ -728,8 +736,6 @@ int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream) {
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
   return lb_pf_set_tile(h, bty, bch);
 }
 

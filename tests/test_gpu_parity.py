@@ -445,6 +445,23 @@ def test_batched_fp64_matches_oracle(gpu, oracle_mod):
         assert ep <= FP64_TOL and eu <= FP64_TOL
 
 
+def test_autotune_3d_keeps_results(gpu):
+    """The autotuner steps the simulation through every candidate shape and
+    keeps a valid one; the state equals, bitwise, an untuned run of the same
+    number of steps (every tile shape gives the same result)."""
+    cfg = W.small_3d(storage="fp16", nx=70, ny=37, nz=29, radius=6)
+    _say(_case(cfg, 0) + " autotune")
+    sim = gpu.Simulation(cfg)
+    sim.autotune(1)
+    ty, ch = sim.get_tile()
+    assert ty in (4, 8, 12) and 1 <= ch <= cfg.nz
+    n = sim.step_count
+    assert n == 3 * 3 * 4  # three times one trial step for 3 heights x 4 chunk lengths
+    phi, u, _ = sim.fields()
+    _, p1, u1, _ = _gpu_run(gpu, cfg, n)
+    assert np.array_equal(phi.cpu().numpy(), p1) and np.array_equal(u.cpu().numpy(), u1)
+
+
 def test_batched_autotune_and_chunks(gpu):
     cfgs = _uneven_ensemble("fp32")
     _say("batched autotune, then chunk 8 and 128")
