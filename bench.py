@@ -439,7 +439,20 @@ def cpu_baseline(cfg_full, sample_n: int, sample_steps: int):
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": cfg.nodes * sample_steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{sample_n}^3 box of the same workload (seed centred), {sample_steps} FP64 steps, "
-                      f"{dt:.1f} s"}
+                      f"{dt:.1f} s",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (what lscpu prints as 'Model name')."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 # -- rocprofv3 summaries ---------------------------------------------------------

@@ -73,9 +73,9 @@ extern "C" {
  * planes XY, YZ and XZ (Sec. 5).  The state beyond those planes is the mirror
  * image of the state inside (phi, u, the index and, for population i, the
  * population of the mirrored direction at the mirror node); the far walls are
- * zero flux.  Seeds belong at the origin or are mirrored with it; the
- * anisotropy must be symmetric about the planes for the octant to stand for
- * the whole domain. */
+ * zero flux.  Seeds belong at the origin or are mirrored with it; every
+ * anisotropy entry must be symmetric about the planes, for the octant to stand
+ * for the whole domain (LBPF_ERR_UNSUPPORTED otherwise; see lbpf_aniso). */
 #define LBPF_PERIODIC 0
 #define LBPF_ZERO_FLUX 1
 #define LBPF_MIRROR_LOW 2
@@ -105,12 +105,25 @@ extern "C" {
 #define LBPF_ANISO_CUBIC_S 4   /* 1 + 66 gamma n_x^2 n_y^2 n_z^2: Eq. As_Function_S, read with the
                                   constant 1 (the printed 66 gamma S vanishes on the axes) */
 
+/* One anisotropy entry.  The entry is the polynomial of its kind evaluated at
+ * R n, a_s(n) = A(R n), so that every crystal of the index field can have its
+ * own orientation in 3D as well (Sec. 4.3, Eq. As_Multi, where each crystal
+ * carries its own angle; R generalises that angle to a rotation).  R is
+ * row-major and must be orthogonal (|R^T R - I| <= 1e-9, else LBPF_ERR_ARG);
+ * all nine zero means the identity.  Every entry must keep a_s > 0 on the unit
+ * sphere (the unit circle in 2D), checked on a fixed set of 4026 directions
+ * (1448 in 2D): otherwise LBPF_ERR_UNSTABLE, since eta_phi = a_s^2 Dphi/e^2 +
+ * 1/2 and the division by a_s^2 of Eq. LBE_Eq_Phase break down.  Under
+ * LBPF_MIRROR_LOW every entry must be symmetric about the mirror planes
+ * (a_s unchanged when n_x, n_y or, in 3D, n_z changes sign; checked on the
+ * same directions to 1e-12): otherwise LBPF_ERR_UNSUPPORTED. */
 typedef struct {
   int32_t kind;
   int32_t q;     /* sectoral order, >= 1 */
   double eps;
   double gamma;  /* CUBIC_HAK and CUBIC_S */
   double phi0;   /* sectoral reference angle, radians */
+  double R[9];   /* orientation, row-major; all zero = identity */
 } lbpf_aniso;
 
 typedef struct {
@@ -192,8 +205,14 @@ int lb_pf_export_dists(lbpf_handle *h, int sim, double *g_dev, double *f_dev, vo
 int lb_pf_import_fields(lbpf_handle *h, int sim, const double *phi_dev, const double *u_dev,
                         const int16_t *ids_dev, void *hip_stream);
 
-/* Checkpoint: the complete state (all fields of every simulation plus the
- * step counter) as one opaque device blob of lb_pf_state_bytes() bytes. */
+/* Checkpoint: the complete state as one opaque device blob of
+ * lb_pf_state_bytes() bytes: a 256-byte header (the step counter and a
+ * fingerprint of every simulation's extents, lattice, storage and index field)
+ * followed by all fields of every simulation.  dev_buf is caller-owned device
+ * memory, 8-byte aligned.  lb_pf_save_state enqueues the copy on hip_stream.
+ * lb_pf_load_state synchronises hip_stream to read the header, returns
+ * LBPF_ERR_ARG (state unchanged) when the blob was not saved from a handle of
+ * the same layout, then enqueues the copy and restores the step counter. */
 int lb_pf_state_bytes(const lbpf_handle *h, size_t *bytes);
 int lb_pf_save_state(lbpf_handle *h, void *dev_buf, size_t bytes, void *hip_stream);
 int lb_pf_load_state(lbpf_handle *h, const void *dev_buf, size_t bytes, void *hip_stream);

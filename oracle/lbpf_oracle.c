@@ -206,7 +206,7 @@ static double lat_sum(const lat_t *L, const double *v) {
 /* Anisotropy functions (Sec. 4.1).  a = A(n); G = gradient of the          */
 /* polynomial A with respect to n (only its tangential part is used).       */
 /* ------------------------------------------------------------------------ */
-void orc_aniso_eval(const orc_aniso *an, const double n[3], double *a, double G[3]) {
+static void poly_eval(const orc_aniso *an, const double n[3], double *a, double G[3]) {
   G[0] = G[1] = G[2] = 0.0;
   if (an == NULL || an->kind == ORC_ANISO_ISO) {
     *a = 1.0;
@@ -263,6 +263,98 @@ void orc_aniso_eval(const orc_aniso *an, const double n[3], double *a, double G[
   G[0] = eps * dQx + gam * (3.0 * dQx + 66.0 * dSx);
   G[1] = eps * dQy + gam * (3.0 * dQy + 66.0 * dSy);
   G[2] = eps * dQz + gam * (3.0 * dQz + 66.0 * dSz);
+}
+
+static int has_rotation(const orc_aniso *an) {
+  for (int k = 0; k < 9; ++k)
+    if (an->R[k] != 0.0) return 1;
+  return 0;
+}
+
+/* The entry's orientation: a(n) = A(R n) for the polynomial A of its kind, and
+ * by the chain rule grad_n a = R^T (grad A)(R n). */
+void orc_aniso_eval(const orc_aniso *an, const double n[3], double *a, double G[3]) {
+  if (an == NULL || an->kind == ORC_ANISO_ISO || !has_rotation(an)) {
+    poly_eval(an, n, a, G);
+    return;
+  }
+  const double *R = an->R;
+  double m[3], Gm[3];
+  for (int r = 0; r < 3; ++r) m[r] = (R[3 * r] * n[0] + R[3 * r + 1] * n[1]) + R[3 * r + 2] * n[2];
+  poly_eval(an, m, a, Gm);
+  for (int c = 0; c < 3; ++c) G[c] = (R[c] * Gm[0] + R[3 + c] * Gm[1]) + R[6 + c] * Gm[2];
+}
+
+/* Unit directions on which entries are checked: a Fibonacci lattice of 4000
+ * points on the sphere plus the 26 neighbour directions of a cube (3D), or
+ * 1440 evenly spaced points on the circle plus the 8 neighbour directions
+ * (2D).  Returns the count; dirs holds at most 4026 directions. */
+static int check_dirs(int dim, double (*dirs)[3]) {
+  const double pi = 3.14159265358979323846;
+  int k = 0;
+  if (dim == 2) {
+    for (int j = 0; j < 1440; ++j) {
+      const double t = 2.0 * pi * (j + 0.5) / 1440.0;
+      dirs[k][0] = cos(t);
+      dirs[k][1] = sin(t);
+      dirs[k][2] = 0.0;
+      ++k;
+    }
+  } else {
+    const double golden = pi * (3.0 - sqrt(5.0));
+    for (int j = 0; j < 4000; ++j) {
+      const double z = 1.0 - (2.0 * j + 1.0) / 4000.0;
+      const double r = sqrt(1.0 - z * z);
+      dirs[k][0] = r * cos(golden * j);
+      dirs[k][1] = r * sin(golden * j);
+      dirs[k][2] = z;
+      ++k;
+    }
+  }
+  for (int x = -1; x <= 1; ++x)
+    for (int y = -1; y <= 1; ++y)
+      for (int z = -1; z <= 1; ++z) {
+        if ((x == 0 && y == 0 && z == 0) || (dim == 2 && z != 0)) continue;
+        const double l = sqrt((double)(x * x + y * y + z * z));
+        dirs[k][0] = x / l;
+        dirs[k][1] = y / l;
+        dirs[k][2] = z / l;
+        ++k;
+      }
+  return k;
+}
+
+double orc_aniso_min(const orc_aniso *an, int dim) {
+  double(*dirs)[3] = malloc(sizeof(double[4026][3]));
+  if (!dirs) return NAN;
+  const int n = check_dirs(dim, dirs);
+  double lo = HUGE_VAL;
+  for (int j = 0; j < n; ++j) {
+    double a, G[3];
+    orc_aniso_eval(an, dirs[j], &a, G);
+    if (!(a >= lo)) lo = a; /* a NaN propagates */
+  }
+  free(dirs);
+  return lo;
+}
+
+int orc_aniso_mirror_symmetric(const orc_aniso *an, int dim) {
+  double(*dirs)[3] = malloc(sizeof(double[4026][3]));
+  if (!dirs) return 0;
+  const int n = check_dirs(dim, dirs);
+  int sym = 1;
+  for (int j = 0; j < n && sym; ++j) {
+    double a, G[3];
+    orc_aniso_eval(an, dirs[j], &a, G);
+    for (int k = 0; k < dim; ++k) {
+      double m[3] = {dirs[j][0], dirs[j][1], dirs[j][2]}, b;
+      m[k] = -m[k];
+      orc_aniso_eval(an, m, &b, G);
+      if (!(fabs(a - b) <= 1e-12)) sym = 0;
+    }
+  }
+  free(dirs);
+  return sym;
 }
 
 /* N of Eq. TermesAnisotropes for a gradient p (lattice units), with
@@ -756,6 +848,13 @@ int orc_create(const orc_config *cfg, orc_sim **out) {
   }
   if (cfg->use_ids && cfg->aniso[0].kind != ORC_ANISO_ISO) return -1;
   if (cfg->mirror_low && cfg->periodic) return -1;
+  for (int k = 0; k < cfg->n_aniso; ++k) {
+    /* a_s > 0 in every direction: eta_phi and the division by a_s^2 of
+     * Eq. LBE_Eq_Phase need it */
+    if (!(orc_aniso_min(&cfg->aniso[k], cfg->dim) > 0.0)) return -2;
+    /* an octant stands for the symmetric domain only if every entry is */
+    if (cfg->mirror_low && !orc_aniso_mirror_symmetric(&cfg->aniso[k], cfg->dim)) return -6;
+  }
   for (int k = 0; k < cfg->n_seeds; ++k)
     if (cfg->seeds[k].id < 0 || (cfg->use_ids && cfg->seeds[k].id >= cfg->n_aniso)) return -1;
 
@@ -782,7 +881,7 @@ int orc_create(const orc_config *cfg, orc_sim **out) {
   S->kphi = S->Dphi * S->lp.inv_e2;
   S->W0lu = cfg->W0 / cfg->dx;
   if (!(S->eta_u > 0.5)) {
-    free(S);
+    orc_destroy(S);
     return -2;
   }
   const long N = S->N;

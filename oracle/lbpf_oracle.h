@@ -32,12 +32,18 @@ enum {
   ORC_ANISO_CUBIC_S = 4    /* 1 + 66 gamma n_x^2 n_y^2 n_z^2: Eq. As_Function_S (printed without the 1) */
 };
 
+/* An entry is the polynomial of its kind evaluated at R n: a(n) = A(R n), so
+ * that each crystal of the index field may have its own orientation (Sec. 4.3,
+ * Eq. As_Multi, generalised from the 2D angle phi0 to a 3D rotation).  R is
+ * row-major; all nine zero means the identity.  The gradient of a with respect
+ * to n is then R^T (grad A)(R n). */
 typedef struct {
   int32_t kind;
   int32_t q;
   double eps;
   double gamma;
   double phi0;
+  double R[9];
 } orc_aniso;
 
 typedef struct {
@@ -72,7 +78,11 @@ typedef struct {
   double nonfinite;
 } orc_diag;
 
-/* Returns 0 on success, negative on a bad configuration. */
+/* Returns 0 on success, negative on a bad configuration: -1 bad argument, -2
+ * unstable (eta_u <= 1/2, or an anisotropy entry with a_s <= 0 on some
+ * direction, where eta_phi and the division by a_s^2 break down), -3 out of
+ * memory, -6 a mirror box whose anisotropy entries are not symmetric about the
+ * mirror planes (the octant would not stand for a symmetric domain). */
 int orc_create(const orc_config *cfg, orc_sim **out);
 void orc_destroy(orc_sim *s);
 int orc_step(orc_sim *s, int nsteps);
@@ -102,6 +112,11 @@ void orc_diagnostics(const orc_sim *s, orc_diag *d);
 int orc_lattice(int which, int *q, int *e /* [q][3] */, double *w, int *opp, double *e2);
 void orc_aniso_eval(const orc_aniso *an, const double n[3], double *a, double G[3]);
 void orc_flux(const orc_aniso *an, const double p[3], double *a, double N[3]);
+/* Smallest a_s of an entry over a fixed set of unit directions (the circle
+ * n_z = 0 when dim == 2), and whether a_s is unchanged by the reflections
+ * n_k -> -n_k of the axes of the box (x, y, and z when dim == 3). */
+double orc_aniso_min(const orc_aniso *an, int dim);
+int orc_aniso_mirror_symmetric(const orc_aniso *an, int dim);
 
 /* Sharp-interface mapping (Sec. 2, Eqs. Capillary-Length and Kinetic-Coeff):
  * out = {d0, beta, lambda_star (beta = 0), a1}. */

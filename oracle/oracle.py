@@ -20,7 +20,7 @@ _KIND = {"iso": 0, "sectoral": 1, "cubic": 2, "cubic_hak": 3, "cubic_s": 4}
 
 class OrcAniso(C.Structure):
     _fields_ = [("kind", C.c_int32), ("q", C.c_int32), ("eps", C.c_double),
-                ("gamma", C.c_double), ("phi0", C.c_double)]
+                ("gamma", C.c_double), ("phi0", C.c_double), ("R", C.c_double * 9)]
 
 
 class OrcSeed(C.Structure):
@@ -81,6 +81,10 @@ def load(build_if_missing: bool = True):
     lib.orc_lattice.restype = C.c_int
     lib.orc_aniso_eval.argtypes = [C.POINTER(OrcAniso), dp, dp, dp]
     lib.orc_flux.argtypes = [C.POINTER(OrcAniso), dp, dp, dp]
+    lib.orc_aniso_min.argtypes = [C.POINTER(OrcAniso), C.c_int]
+    lib.orc_aniso_min.restype = C.c_double
+    lib.orc_aniso_mirror_symmetric.argtypes = [C.POINTER(OrcAniso), C.c_int]
+    lib.orc_aniso_mirror_symmetric.restype = C.c_int
     lib.orc_sharp_interface.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, dp]
     _lib = lib
     return lib
@@ -92,7 +96,10 @@ def _dptr(a: np.ndarray):
 
 
 def _aniso_struct(a) -> OrcAniso:
-    return OrcAniso(_KIND[a.kind], int(a.q), float(a.eps), float(a.gamma), float(a.phi0))
+    R = getattr(a, "R", None)
+    R = [0.0] * 9 if R is None else [float(v) for v in R]
+    return OrcAniso(_KIND[a.kind], int(a.q), float(a.eps), float(a.gamma), float(a.phi0),
+                    (C.c_double * 9)(*R))
 
 
 class OracleSim:
@@ -124,7 +131,9 @@ class OracleSim:
         h = C.c_void_p()
         rc = self.lib.orc_create(C.byref(c), C.byref(h))
         if rc != 0:
-            raise ValueError(f"orc_create failed: {rc}")
+            err = ValueError(f"orc_create failed: {rc}")
+            err.code = rc
+            raise err
         self.h = h
         self.N = int(self.lib.orc_nodes(h))
         self.q_phi = int(self.lib.orc_q_phi(h))
@@ -235,3 +244,15 @@ def sharp_interface(W0, tau0, lam, kappa):
     out = np.zeros(4)
     lib.orc_sharp_interface(float(W0), float(tau0), float(lam), float(kappa), _dptr(out))
     return tuple(float(v) for v in out)
+
+
+def aniso_min(entry, dim: int = 3) -> float:
+    """Smallest a_s of the entry over the oracle's fixed direction set."""
+    s = _aniso_struct(entry)
+    return float(load().orc_aniso_min(C.byref(s), int(dim)))
+
+
+def aniso_mirror_symmetric(entry, dim: int = 3) -> bool:
+    """Whether a_s is unchanged by n_k -> -n_k for every axis of the box."""
+    s = _aniso_struct(entry)
+    return bool(load().orc_aniso_mirror_symmetric(C.byref(s), int(dim)))

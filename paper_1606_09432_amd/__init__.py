@@ -41,7 +41,7 @@ EXPORTED_SYMBOLS = (
 
 class LbpfAniso(C.Structure):
     _fields_ = [("kind", C.c_int32), ("q", C.c_int32), ("eps", C.c_double), ("gamma", C.c_double),
-                ("phi0", C.c_double)]
+                ("phi0", C.c_double), ("R", C.c_double * 9)]
 
 
 class LbpfSeed(C.Structure):
@@ -131,7 +131,8 @@ def sharp_interface(W0: float, tau0: float, lam: float, kappa: float):
 def _to_struct(cfg: SimConfig, keep: list) -> LbpfConfig:
     cfg.validate()
     an = (LbpfAniso * len(cfg.aniso))(*[LbpfAniso(ANISO[a.kind], int(a.q), float(a.eps), float(a.gamma),
-                                                  float(a.phi0)) for a in cfg.aniso])
+                                                  float(a.phi0), (C.c_double * 9)(*a.rotation_row_major()))
+                                        for a in cfg.aniso])
     sd = (LbpfSeed * max(1, len(cfg.seeds)))(*[LbpfSeed(float(s.x), float(s.y), float(s.z), float(s.radius),
                                                         int(s.id)) for s in cfg.seeds])
     keep.extend([an, sd])

@@ -1,6 +1,7 @@
 // C ABI of the library (include/lb_pf.h): configuration checks, lattice-unit
 // conversion, workspace layout, launches and diagnostics.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -86,6 +87,93 @@ struct lbpf_handle {
 
 namespace {
 
+// Device form of an entry: cos and sin of q phi0, and the orientation R (an
+// all-zero R is the identity, kept as rot = 0 so that the step skips it).
+AnisoDev to_dev(const lbpf_aniso &a) {
+  AnisoDev d{};
+  d.kind = a.kind;
+  d.q = a.q;
+  d.eps = a.eps;
+  d.gamma = a.gamma;
+  d.cr = std::cos(a.q * a.phi0);
+  d.ci = -std::sin(a.q * a.phi0);
+  d.rot = 0;
+  for (int k = 0; k < 9; ++k) {
+    d.R[k] = a.R[k];
+    if (a.R[k] != 0.0) d.rot = 1;
+  }
+  return d;
+}
+
+// The unit directions on which entries are checked: 4000 points of a
+// Fibonacci lattice on the sphere and the 26 neighbour directions of a cube
+// in 3D; 1440 evenly spaced points on the circle and its 8 neighbour
+// directions in 2D.
+std::vector<std::array<double, 3>> check_dirs(int dim) {
+  std::vector<std::array<double, 3>> v;
+  const double pi = 3.14159265358979323846;
+  if (dim == 2) {
+    for (int j = 0; j < 1440; ++j) {
+      const double t = 2.0 * pi * (j + 0.5) / 1440.0;
+      v.push_back({std::cos(t), std::sin(t), 0.0});
+    }
+  } else {
+    const double ga = pi * (3.0 - std::sqrt(5.0));
+    for (int j = 0; j < 4000; ++j) {
+      const double z = 1.0 - (2.0 * j + 1.0) / 4000.0, r = std::sqrt(1.0 - z * z);
+      v.push_back({r * std::cos(ga * j), r * std::sin(ga * j), z});
+    }
+  }
+  for (int x = -1; x <= 1; ++x)
+    for (int y = -1; y <= 1; ++y)
+      for (int z = -1; z <= 1; ++z) {
+        if ((x | y | z) == 0 || (dim == 2 && z != 0)) continue;
+        const double l = std::sqrt(double(x * x + y * y + z * z));
+        v.push_back({x / l, y / l, z / l});
+      }
+  return v;
+}
+
+double entry_a(const AnisoDev &d, const std::array<double, 3> &n) {
+  if (d.kind == LBPF_ANISO_ISO) return 1.0;
+  double a, gx, gy, gz;
+  aniso_eval_rot<double>(d, n[0], n[1], n[2], a, gx, gy, gz);
+  return a;
+}
+
+int check_entry(const lbpf_aniso &a, int dim, bool mirror) {
+  double rr = 0;  // |R^T R - I| (max element) when a rotation is given
+  bool any = false;
+  for (int k = 0; k < 9; ++k) {
+    if (!std::isfinite(a.R[k])) return fail(LBPF_ERR_ARG, "anisotropy rotation must be finite");
+    any = any || a.R[k] != 0.0;
+  }
+  if (any) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        double t = 0;
+        for (int k = 0; k < 3; ++k) t += a.R[3 * k + i] * a.R[3 * k + j];
+        rr = std::max(rr, std::fabs(t - (i == j ? 1.0 : 0.0)));
+      }
+    if (!(rr <= 1e-9)) return fail(LBPF_ERR_ARG, "anisotropy rotation R is not orthogonal");
+  }
+  const AnisoDev d = to_dev(a);
+  for (const auto &n : check_dirs(dim)) {
+    const double v = entry_a(d, n);
+    if (!(v > 0.0)) return fail(LBPF_ERR_UNSTABLE, "anisotropy entry with a_s <= 0 in some direction");
+    if (mirror) {
+      for (int k = 0; k < dim; ++k) {
+        std::array<double, 3> m = n;
+        m[k] = -m[k];
+        if (!(std::fabs(entry_a(d, m) - v) <= 1e-12))
+          return fail(LBPF_ERR_UNSUPPORTED,
+                      "mirror planes need anisotropy entries symmetric about them (a_s(n) = a_s(n reflected))");
+      }
+    }
+  }
+  return LBPF_OK;
+}
+
 int validate(const lbpf_config &c) {
   if (c.lattice != LBPF_D2Q9_D2Q5 && c.lattice != LBPF_D3Q19_D3Q7 && c.lattice != LBPF_D3Q15_D3Q7)
     return fail(LBPF_ERR_ARG, "unknown lattice");
@@ -121,6 +209,8 @@ int validate(const lbpf_config &c) {
     if (a.kind == LBPF_ANISO_SECTORAL && (a.q < 1 || a.q > 64)) return fail(LBPF_ERR_ARG, "sectoral q must be 1..64");
     if (!std::isfinite(a.eps) || !std::isfinite(a.gamma) || !std::isfinite(a.phi0))
       return fail(LBPF_ERR_ARG, "anisotropy parameters must be finite");
+    const int rc = check_entry(a, dim, c.boundary == LBPF_MIRROR_LOW);
+    if (rc) return rc;
   }
   if (c.use_ids && c.aniso[0].kind != LBPF_ANISO_ISO)
     return fail(LBPF_ERR_ARG, "with the index field, entry 0 must be isotropic");
@@ -408,15 +498,7 @@ int lb_pf_init(const lbpf_config *cfgs, int n_sims, void *dev_workspace, size_t 
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   for (SimHost &s : h->sims) {
     std::vector<AnisoDev> tab(s.cfg.n_aniso);
-    for (int k = 0; k < s.cfg.n_aniso; ++k) {
-      const lbpf_aniso &a = s.aniso[k];
-      tab[k].kind = a.kind;
-      tab[k].q = a.q;
-      tab[k].eps = a.eps;
-      tab[k].gamma = a.gamma;
-      tab[k].cr = std::cos(a.q * a.phi0);
-      tab[k].ci = -std::sin(a.q * a.phi0);
-    }
+    for (int k = 0; k < s.cfg.n_aniso; ++k) tab[k] = to_dev(s.aniso[k]);
     std::vector<SeedDev> sd(std::max(1, s.cfg.n_seeds));
     for (int k = 0; k < s.cfg.n_seeds; ++k) {
       sd[k] = SeedDev{s.seeds[k].x, s.seeds[k].y, s.seeds[k].z, s.seeds[k].radius, s.seeds[k].crystal_id};
@@ -630,9 +712,32 @@ int lb_pf_import_fields(lbpf_handle *h, int sim, const double *phi_dev, const do
   return LBPF_OK;
 }
 
+namespace {
+// FNV-1a over what must match between a saved blob and the loading handle.
+unsigned long long state_layout(const lbpf_handle *h) {
+  unsigned long long v = 1469598103934665603ULL;
+  auto mix = [&](long long x) {
+    for (int k = 0; k < 8; ++k) {
+      v ^= (unsigned long long)((x >> (8 * k)) & 0xff);
+      v *= 1099511628211ULL;
+    }
+  };
+  for (const SimHost &s : h->sims) {
+    mix(s.cfg.lattice);
+    mix(s.cfg.nx);
+    mix(s.cfg.ny);
+    mix(s.cfg.nz);
+    mix(s.storage);
+    mix(s.cfg.use_ids);
+    mix((long long)s.state_bytes);
+  }
+  return v;
+}
+}  // namespace
+
 int lb_pf_state_bytes(const lbpf_handle *h, size_t *bytes) {
   if (!h || !bytes) return fail(LBPF_ERR_ARG, "null argument");
-  size_t b = 0;
+  size_t b = kStateHeaderBytes;
   for (const SimHost &s : h->sims) b += s.state_bytes;
   *bytes = b;
   return LBPF_OK;
@@ -643,10 +748,14 @@ int lb_pf_save_state(lbpf_handle *h, void *dev_buf, size_t bytes, void *hip_stre
   int rc = lb_pf_state_bytes(h, &need);
   if (rc) return rc;
   if (!dev_buf || bytes < need) return fail(LBPF_ERR_ARG, "state buffer too small");
-  char *dst = static_cast<char *>(dev_buf);
+  if (reinterpret_cast<uintptr_t>(dev_buf) % 8 != 0) return fail(LBPF_ERR_ARG, "state buffer not 8-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  StateHeader hd{kStateMagic, 1, (long long)h->sims.size(), (long long)h->step, (unsigned long long)need,
+                 state_layout(h)};
+  HIPCHK(launch_state_header(static_cast<StateHeader *>(dev_buf), hd, st));
+  char *dst = static_cast<char *>(dev_buf) + kStateHeaderBytes;
   for (const SimHost &s : h->sims) {
-    HIPCHK(hipMemcpyAsync(dst, h->ws + s.state_off[h->parity], s.state_bytes, hipMemcpyDeviceToDevice,
-                          static_cast<hipStream_t>(hip_stream)));
+    HIPCHK(hipMemcpyAsync(dst, h->ws + s.state_off[h->parity], s.state_bytes, hipMemcpyDeviceToDevice, st));
     dst += s.state_bytes;
   }
   return LBPF_OK;
@@ -657,12 +766,19 @@ int lb_pf_load_state(lbpf_handle *h, const void *dev_buf, size_t bytes, void *hi
   int rc = lb_pf_state_bytes(h, &need);
   if (rc) return rc;
   if (!dev_buf || bytes < need) return fail(LBPF_ERR_ARG, "state buffer too small");
-  const char *src = static_cast<const char *>(dev_buf);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  StateHeader hd{};
+  HIPCHK(hipMemcpyAsync(&hd, dev_buf, sizeof(hd), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (hd.magic != kStateMagic || hd.version != 1 || hd.n_sims != (long long)h->sims.size() ||
+      hd.bytes != (unsigned long long)need || hd.layout != state_layout(h) || hd.step < 0)
+    return fail(LBPF_ERR_ARG, "the blob is not a checkpoint of a handle with this layout");
+  const char *src = static_cast<const char *>(dev_buf) + kStateHeaderBytes;
   for (const SimHost &s : h->sims) {
-    HIPCHK(hipMemcpyAsync(h->ws + s.state_off[h->parity], src, s.state_bytes, hipMemcpyDeviceToDevice,
-                          static_cast<hipStream_t>(hip_stream)));
+    HIPCHK(hipMemcpyAsync(h->ws + s.state_off[h->parity], src, s.state_bytes, hipMemcpyDeviceToDevice, st));
     src += s.state_bytes;
   }
+  h->step = hd.step;
   return LBPF_OK;
 }
 

@@ -361,4 +361,16 @@ hipError_t launch_export(int lattice, int storage, const SimDev &sd, double *phi
   return hipErrorInvalidValue;
 }
 
+// ---------------------------------------------------------------------------
+// Checkpoint header: one thread stores the record passed as an argument.
+// ---------------------------------------------------------------------------
+__global__ void state_header_kernel(StateHeader *dst, StateHeader h) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *dst = h;
+}
+
+hipError_t launch_state_header(StateHeader *dst, const StateHeader &h, hipStream_t st) {
+  hipLaunchKernelGGL(state_header_kernel, dim3(1), dim3(64), 0, st, dst, h);
+  return hipGetLastError();
+}
+
 }  // namespace lbpf

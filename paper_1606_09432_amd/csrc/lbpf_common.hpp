@@ -176,11 +176,15 @@ struct StF16 {
   static __device__ __forceinline__ T dec(S s) { return __half2float(s); }
 };
 
-// Anisotropy entry as the kernels see it (cos/sin of q phi0 precomputed on the host).
+// Anisotropy entry as the kernels see it (cos/sin of q phi0 precomputed on the
+// host).  rot = 1: the polynomial is evaluated at R n (R row-major), a crystal
+// orientation of Sec. 4.3 in 3D; rot = 0 skips the rotation (identity).
 struct AnisoDev {
   int kind;
   int q;
   double eps, gamma, cr, ci;
+  int rot;
+  double R[9];
 };
 constexpr int kMaxAniso = 256;
 
@@ -243,8 +247,8 @@ __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(
 // Anisotropy functions (Sec. 4.1): value a and gradient G of the polynomial in n.
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ __forceinline__ void aniso_eval(const AnisoDev &A, T nx, T ny, T nz, T &a, T &Gx, T &Gy,
-                                           T &Gz) {
+__host__ __device__ __forceinline__ void aniso_eval(const AnisoDev &A, T nx, T ny, T nz, T &a, T &Gx, T &Gy,
+                                                    T &Gz) {
   Gx = Gy = Gz = T(0);
   if (A.kind == K_SECTORAL) {
     // Re[z^q c] with z = n_x + i n_y, c = e^{-i q phi0}; gradient Re[q z^{q-1} c], -Im[q z^{q-1} c].
@@ -296,6 +300,25 @@ __device__ __forceinline__ void aniso_eval(const AnisoDev &A, T nx, T ny, T nz, 
   a = T(1);
 }
 
+// An entry at direction n: the polynomial at m = R n, and by the chain rule
+// the gradient with respect to n, R^T (grad A)(m).
+template <class T>
+__host__ __device__ __forceinline__ void aniso_eval_rot(const AnisoDev &A, T nx, T ny, T nz, T &a, T &Gx, T &Gy,
+                                                        T &Gz) {
+  if (!A.rot) {
+    aniso_eval<T>(A, nx, ny, nz, a, Gx, Gy, Gz);
+    return;
+  }
+  const T mx = (T(A.R[0]) * nx + T(A.R[1]) * ny) + T(A.R[2]) * nz;
+  const T my = (T(A.R[3]) * nx + T(A.R[4]) * ny) + T(A.R[5]) * nz;
+  const T mz = (T(A.R[6]) * nx + T(A.R[7]) * ny) + T(A.R[8]) * nz;
+  T Hx, Hy, Hz;
+  aniso_eval<T>(A, mx, my, mz, a, Hx, Hy, Hz);
+  Gx = (T(A.R[0]) * Hx + T(A.R[3]) * Hy) + T(A.R[6]) * Hz;
+  Gy = (T(A.R[1]) * Hx + T(A.R[4]) * Hy) + T(A.R[7]) * Hz;
+  Gz = (T(A.R[2]) * Hx + T(A.R[5]) * Hy) + T(A.R[8]) * Hz;
+}
+
 // a_s and N = -|p| a (G - n (n.G)) for the gradient p, n = -p/|p|
 // (Eqs. Def_Normal_Vector, TermesAnisotropes).  Isotropic where |p| <= 1e-8
 // (lattice units): below that the direction of p is set by the rounding of
@@ -311,7 +334,7 @@ __device__ __forceinline__ void flux(const AnisoDev *A, T px, T py, T pz, T &a, 
   const T r = r2 * ir;
   const T nx = -px * ir, ny = -py * ir, nz = -pz * ir;
   T Gx, Gy, Gz;
-  aniso_eval<T>(*A, nx, ny, nz, a, Gx, Gy, Gz);
+  aniso_eval_rot<T>(*A, nx, ny, nz, a, Gx, Gy, Gz);
   const T nG = (nx * Gx + ny * Gy) + nz * Gz;
   const T ra = r * a;
   Nx = -ra * (Gx - nx * nG);

@@ -42,6 +42,22 @@ struct InitSrc {
 constexpr int kDiagVals = 6;
 constexpr int kDiagBlocks = 512;
 
+// Head of a checkpoint blob: what the state blocks after it belong to, and the
+// step counter.  The blob starts with kStateHeaderBytes bytes holding it.
+struct StateHeader {
+  unsigned long long magic;   // kStateMagic
+  long long version;          // 1
+  long long n_sims;
+  long long step;             // step counter of the saved state
+  unsigned long long bytes;   // size of the whole blob
+  unsigned long long layout;  // hash of every simulation's extents, lattice, storage and block size
+};
+constexpr unsigned long long kStateMagic = 0x5441545346504c42ULL;  // "BLPFSTAT"
+constexpr size_t kStateHeaderBytes = 256;
+
+// Writes h to device memory dst (stream-ordered; h travels as a kernel argument).
+hipError_t launch_state_header(StateHeader *dst, const StateHeader &h, hipStream_t st);
+
 // lattice: pair code (0 D2Q9/D2Q5, 1 D3Q19/D3Q7, 2 D3Q15/D3Q7).
 hipError_t launch_step(int lattice, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st);
 // sims: the SimDev of every simulation for the step's parity (device memory);

@@ -21,7 +21,7 @@ from __future__ import annotations
 import dataclasses
 import math
 from dataclasses import dataclass, field
-from typing import List, Tuple
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -47,6 +47,23 @@ class Aniso:
     q: int = 4
     phi0: float = 0.0
     gamma: float = 0.0
+    # orientation of the crystal: the polynomial is evaluated at R n (R given
+    # row-major, 9 values); None is the identity
+    R: Optional[Tuple[float, ...]] = None
+
+    def rotation_row_major(self) -> List[float]:
+        """The 9 values of R, or 9 zeros (the C structs' code for the identity)."""
+        return [0.0] * 9 if self.R is None else [float(v) for v in self.R]
+
+
+def rotation(axis: Tuple[float, float, float], angle: float) -> Tuple[float, ...]:
+    """Row-major matrix of the rotation by `angle` (radians) about `axis`
+    (Rodrigues' formula); an input-description helper for oriented crystals."""
+    a = np.asarray(axis, dtype=np.float64)
+    a = a / np.linalg.norm(a)
+    K = np.array([[0.0, -a[2], a[1]], [a[2], 0.0, -a[0]], [-a[1], a[0], 0.0]])
+    R = np.eye(3) + math.sin(angle) * K + (1.0 - math.cos(angle)) * (K @ K)
+    return tuple(float(v) for v in R.ravel())
 
 
 @dataclass
@@ -264,14 +281,36 @@ def paper3d_octant(storage: str = "fp64", n: int = 351) -> SimConfig:
 
 
 def multi_3d(storage: str = "fp64", lattice: str = "D3Q19_D3Q7", gradient: str = "dd",
-             shape=(48, 44, 40), boundary: str = "zero_flux") -> SimConfig:
+             shape=(48, 44, 40), boundary: str = "zero_flux", y66_phi0: float = 0.3) -> SimConfig:
     """A small 3D box with three crystals, each with its own anisotropy entry
-    in the crystal index field (Sec. 4.3): cubic, Eq. As_MatSci and Eq. As_Y66."""
+    in the crystal index field (Sec. 4.3): cubic, Eq. As_MatSci and Eq. As_Y66
+    turned by y66_phi0 about z (0 keeps every entry symmetric about the
+    coordinate planes, as a box with mirror planes requires)."""
     nx, ny, nz = shape
     aniso = [Aniso("iso"), Aniso("cubic", eps=0.05), Aniso("cubic_hak", eps=0.1, gamma=0.0),
-             Aniso("sectoral", eps=0.05, q=6, phi0=0.3)]
+             Aniso("sectoral", eps=0.05, q=6, phi0=y66_phi0)]
     seeds = [Seed(nx * 0.27, ny * 0.3, nz * 0.35, 4.0, 1), Seed(nx * 0.7, ny * 0.33, nz * 0.6, 4.5, 2),
              Seed(nx * 0.45, ny * 0.72, nz * 0.5, 3.5, 3)]
+    return SimConfig(
+        lattice=lattice, nx=nx, ny=ny, nz=nz, boundary=boundary, gradient=gradient, storage=storage,
+        delta=0.55, kappa=KAPPA_C0, aniso=aniso, seeds=seeds, use_ids=True, tip_dir=(1, 0, 0))
+
+
+# Orientations of the oriented-crystals workload: rotations about skew axes,
+# so that no crystal shares the lattice's axes or another crystal's.
+ORIENTED_AXES = (((1.0, 1.0, 1.0), 0.4), ((1.0, -2.0, 0.5), 1.1))
+
+
+def oriented_3d(storage: str = "fp64", lattice: str = "D3Q19_D3Q7", gradient: str = "dd",
+                shape=(56, 48, 44), boundary: str = "zero_flux") -> SimConfig:
+    """Three crystals of one cubic-harmonic kind (Eq. As_MatSci, eps = 0.1) in
+    the crystal index field, two of them turned by their own rotation R: the
+    per-crystal orientation of Sec. 4.3 (Eq. As_Multi) in 3D."""
+    nx, ny, nz = shape
+    base = dict(kind="cubic_hak", eps=0.1, gamma=0.0)
+    aniso = [Aniso("iso"), Aniso(**base)] + [Aniso(**base, R=rotation(ax, ang)) for ax, ang in ORIENTED_AXES]
+    seeds = [Seed(nx * 0.27, ny * 0.3, nz * 0.35, 4.5, 1), Seed(nx * 0.7, ny * 0.35, nz * 0.6, 4.5, 2),
+             Seed(nx * 0.45, ny * 0.72, nz * 0.45, 4.5, 3)]
     return SimConfig(
         lattice=lattice, nx=nx, ny=ny, nz=nz, boundary=boundary, gradient=gradient, storage=storage,
         delta=0.55, kappa=KAPPA_C0, aniso=aniso, seeds=seeds, use_ids=True, tip_dir=(1, 0, 0))

@@ -150,3 +150,57 @@ def test_product_never_imports_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"(import\s+oracle|from\s+oracle|lbpf_oracle|orc_\w+\()", txt), f
+
+
+def _ws_rc(lib, cfg):
+    keep = []
+    s = lb._to_struct(cfg, keep)
+    b = C.c_size_t()
+    return lib.lb_pf_workspace_bytes(C.byref(s), 1, C.byref(b))
+
+
+ROT_GENERIC = W.rotation((1.0, 2.0, 3.0), 0.7)
+ROT_Z45 = W.rotation((0.0, 0.0, 1.0), 0.7853981633974483)
+
+
+@pytest.mark.parametrize("entry,dim,code", [
+    (W.Aniso("sectoral", eps=1.2, q=4), 2, -2),        # a_s = 1 - 1.2 on the diagonals
+    (W.Aniso("sectoral", eps=0.9, q=4), 2, 0),
+    (W.Aniso("cubic", eps=0.7), 3, -2),                # 1 - 5 eps / 3 < 0 on <111>
+    (W.Aniso("cubic", eps=0.55), 3, 0),
+    (W.Aniso("cubic_s", gamma=-0.5), 3, -2),           # 1 + 66 gamma / 27 < 0 on <111>
+    (W.Aniso("cubic_hak", eps=0.0, gamma=1.2), 3, -2),  # 1 + gamma (3/2 - 17/7) < 0 on <110>
+    (W.Aniso("cubic", eps=0.05, R=ROT_GENERIC), 3, 0),
+    (W.Aniso("cubic", eps=0.05, R=(1.0, 0.1, 0, 0, 1, 0, 0, 0, 1)), 3, -1),  # not orthogonal
+    (W.Aniso("cubic", eps=0.05, R=(2.0, 0, 0, 0, 2, 0, 0, 0, 2)), 3, -1),
+])
+def test_entries_checked_on_the_sphere(lib, entry, dim, code):
+    """Entries must keep a_s > 0 (LBPF_ERR_UNSTABLE otherwise) and a given R
+    must be orthogonal (LBPF_ERR_ARG)."""
+    cfg = W.c0(n=32) if dim == 2 else W.small_3d(n=8)
+    assert _ws_rc(lib, cfg.replace(aniso=[entry])) == code, lib.lb_pf_last_error()
+
+
+@pytest.mark.parametrize("entry,ok", [
+    (W.Aniso("cubic", eps=0.05), True), (W.Aniso("cubic_hak", eps=0.1, gamma=-0.02), True),
+    (W.Aniso("cubic_s", gamma=0.02), True), (W.Aniso("sectoral", eps=0.05, q=6), True),
+    (W.Aniso("cubic", eps=0.05, R=ROT_Z45), True),
+    (W.Aniso("sectoral", eps=0.05, q=6, phi0=0.3), False), (W.Aniso("sectoral", eps=0.05, q=3), False),
+    (W.Aniso("cubic", eps=0.05, R=ROT_GENERIC), False),
+])
+def test_mirror_boxes_need_symmetric_entries(lib, oracle_mod, entry, ok):
+    """LBPF_MIRROR_LOW refuses entries that are not symmetric about the planes
+    (LBPF_ERR_UNSUPPORTED); zero-flux boxes accept them.  The oracle takes the
+    same decisions."""
+    cfg = W.small_3d(n=10, aniso=entry).replace(seeds=[W.Seed(0, 0, 0, 3.0, 1)])
+    assert _ws_rc(lib, cfg) == 0
+    rc = _ws_rc(lib, cfg.replace(boundary="mirror_low"))
+    assert rc == (0 if ok else -6), lib.lb_pf_last_error()
+    assert oracle_mod.aniso_mirror_symmetric(entry, 3) == ok
+    if not ok:
+        assert "symmetric" in lib.lb_pf_last_error().decode()
+    # 2D: the sectoral four-fold function turned by 0.2 is asymmetric about the axes
+    c2 = W.c0(n=16).replace(boundary="mirror_low", seeds=[W.Seed(0, 0, 0, 3.0, 1)])
+    assert _ws_rc(lib, c2) == 0
+    assert _ws_rc(lib, c2.replace(aniso=[W.Aniso("sectoral", eps=0.05, q=4, phi0=0.2)])) == -6
+

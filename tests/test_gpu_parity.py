@@ -131,6 +131,105 @@ def test_d3q15_fp64_parity(gpu, oracle_mod, boundary, grad, shape, entry, steps)
     _compare(gpu, oracle_mod, cfg, steps)
 
 
+# 64^3 for 200 steps in FP64, both 3D lattice pairs: the benchmark's
+# anisotropy (Eq. As_MatSci, <100> variant) with the undercooling of the
+# 512^3 runs, the seed off-centre so that no symmetry hides an index mistake.
+@pytest.mark.parametrize("lattice,boundary", [("D3Q19_D3Q7", "zero_flux"), ("D3Q15_D3Q7", "zero_flux"),
+                                              ("D3Q19_D3Q7", "periodic")])
+def test_3d_fp64_parity_64_cubed_200_steps(gpu, oracle_mod, lattice, boundary):
+    cfg = W.c3("fp64", "100", n=64).replace(lattice=lattice, boundary=boundary,
+                                              seeds=[W.Seed(29.4, 33.2, 31.7, 8.0, 1)])
+    sim, orc = _compare(gpu, oracle_mod, cfg, 200)
+    dg, do = sim.diagnostics()[0], orc.diagnostics()
+    _say(f"  tip {dg['tip_position']:.6f} / {do['tip_position']:.6f}  n_solid {dg['n_solid']} / {do['n_solid']}")
+    assert do["tip_position"] > 10.0  # the crystal grew
+    assert abs(dg["tip_position"] - do["tip_position"]) < 1e-9 and dg["n_solid"] == do["n_solid"]
+    assert abs(dg["sum_u_minus_half_phi"] - do["sum_u_minus_half_phi"]) < 1e-8
+
+
+# The initial state itself (Sec. 2, Eq. Initial_Condition and Eq.
+# Intial-Cond_u; g = g^(0), f = w_i u): phi, u, the index and the decoded
+# populations at step 0, then after one step.
+@pytest.mark.parametrize("which", ["2d_ids", "3d_oriented", "d3q15", "periodic_2d"])
+def test_initial_state_parity(gpu, oracle_mod, which):
+    if which == "2d_ids":
+        cfg = W.c1(n=96, count=4).replace(seeds=[W.Seed(30.2, 40.7, 0, 9.0, 1), W.Seed(41.3, 44.1, 0, 6.5, 2),
+                                                 W.Seed(70.0, 20.0, 0, 5.0, 3), W.Seed(72.5, 70.25, 0, 4.0, 4)])
+    elif which == "3d_oriented":
+        cfg = W.oriented_3d()
+    elif which == "d3q15":
+        cfg = W.small_3d(n=30, radius=6.3, aniso=W.Aniso("cubic_s", gamma=0.02)).replace(lattice="D3Q15_D3Q7")
+    else:
+        cfg = W.c0(n=64).replace(seeds=[W.Seed(3.0, 60.0, 0, 7.0, 1)])  # wraps around two edges
+    _say(_case(cfg, 0) + f" initial state ({which})")
+    sim = gpu.Simulation(cfg)
+    orc = _oracle_run(oracle_mod, cfg, 0)
+    for steps in (0, 1):
+        phi, u, ids = [t.cpu().numpy() for t in sim.fields()]
+        g, f = [t.cpu().numpy() for t in sim.dists()]
+        ep, eu = np.abs(phi - orc.phi()).max(), np.abs(u - orc.u()).max()
+        eg, ef = np.abs(g - orc.g()).max(), np.abs(f - orc.f()).max()
+        _say(f"  step {steps}: |dphi| {ep:.2e} |du| {eu:.2e} |dg| {eg:.2e} |df| {ef:.2e}")
+        assert ep <= 1e-14 and eu <= 1e-14 and eg <= 1e-14 and ef <= 1e-14
+        if cfg.use_ids:
+            assert np.array_equal(ids, orc.ids())
+            assert len(np.unique(ids)) == len(cfg.seeds) + 1
+        if steps == 0:
+            assert np.all(u == -cfg.delta)
+            sim.step(1)
+            orc.step(1)
+
+
+# Two crystals of one cubic-harmonic kind turned by their own rotations and a
+# third unturned, in the 3D index field (Sec. 4.3, per-crystal orientation).
+@pytest.mark.parametrize("lattice,grad", [("D3Q19_D3Q7", "dd"), ("D3Q15_D3Q7", "dd"), ("D3Q19_D3Q7", "cd")])
+def test_oriented_crystals_parity(gpu, oracle_mod, lattice, grad):
+    cfg = W.oriented_3d(lattice=lattice, gradient=grad)
+    sim, orc = _compare(gpu, oracle_mod, cfg, 150)
+    ids = orc.ids()
+    assert all((ids == k).sum() > 400 for k in (1, 2, 3))
+    # the orientations matter: the same run with every crystal unturned differs
+    if lattice == "D3Q19_D3Q7" and grad == "dd":
+        plain = cfg.replace(aniso=[cfg.aniso[0]] + [W.Aniso("cubic_hak", eps=0.1)] * 3)
+        _, phi2, _, _ = _gpu_run(gpu, plain, 150)
+        assert np.abs(phi2 - orc.phi()).max() > 1e-3
+
+
+@pytest.mark.parametrize("storage,tol", [("fp32", 1e-4), ("fp16", 1e-3)])
+def test_oriented_crystals_offset_storage(gpu, oracle_mod, storage, tol):
+    cfg = W.oriented_3d(storage=storage)
+    _say(_case(cfg, 150))
+    sim, phi, u, _ = _gpu_run(gpu, cfg, 150)
+    orc = _oracle_run(oracle_mod, cfg, 150)
+    ephi, eu = np.abs(phi - orc.phi()).max(), np.abs(u - orc.u()).max()
+    _say(f"  {storage}: max|dphi| = {ephi:.3e} max|du| = {eu:.3e}")
+    assert ephi <= tol and eu <= tol
+
+
+# FP64 diagnostics on imported hand-built fields whose sums are exact in
+# binary: the reductions must return them exactly.
+@pytest.mark.parametrize("cfg", [W.small_3d(n=40, nx=70), W.c0(n=96).replace(ny=130)], ids=["3d", "2d"])
+def test_diagnostics_on_hand_built_fields(gpu, cfg):
+    import torch
+    _say(_case(cfg, 0) + " hand-built diagnostics")
+    rng = np.random.default_rng(12)
+    phi = rng.choice([-1.0, -0.5, 0.0, 0.25, 1.0], size=cfg.shape)
+    u = rng.choice([-0.5, 0.125, 0.375], size=cfg.shape)
+    sim = gpu.Simulation(cfg)
+    sim.import_fields(phi, u)
+    d = sim.diagnostics()[0]
+    assert d["sum_phi"] == float(phi.sum())
+    # u is read back as the sum of its populations w_i u: exact with the D3Q7
+    # weights (1/4, 1/8), within rounding with the D2Q5 ones (1/3, 1/6)
+    tol_u = 0.0 if cfg.dim == 3 else 1e-15 * cfg.nodes
+    assert abs(d["sum_u"] - float(u.sum())) <= tol_u
+    assert abs(d["sum_u_minus_half_phi"] - float((u - 0.5 * phi).sum())) <= tol_u
+    assert d["n_solid"] == float((phi > 0).sum())
+    assert d["solid_fraction"] == float((1.0 + phi).sum()) / (2.0 * cfg.nodes)
+    assert d["nonfinite"] == 0
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("storage,tol", [("fp32", 1e-4), ("fp16", 1e-3)])
 def test_d3q15_offset_storage_accuracy(gpu, oracle_mod, storage, tol):
     cfg = W.small_3d(storage=storage, n=40, radius=6).replace(lattice="D3Q15_D3Q7")
@@ -371,14 +470,33 @@ def test_checkpoint_restart_bitwise(gpu, storage):
     sim.step(30)
     ck = sim.save_state()
     sim.step(20)
+    assert sim.step_count == 50
     a = [t.cpu().numpy() for t in sim.fields()]
     sim.load_state(ck)
+    assert sim.step_count == 30  # the blob carries the step counter
     sim.step(20)
+    assert sim.step_count == 50
     b = [t.cpu().numpy() for t in sim.fields()]
     torch.cuda.synchronize()
     straight = _gpu_run(gpu, cfg, 50)[1:]
     for x, y, z in zip(a, b, straight):
         assert np.array_equal(x, y) and np.array_equal(x, z)
+    # a fresh handle of the same layout resumes at the saved step
+    other = gpu.Simulation(cfg)
+    other.load_state(ck)
+    assert other.step_count == 30 and other.diagnostics()[0]["step"] == 30
+    other.step(20)
+    c = [t.cpu().numpy() for t in other.fields()]
+    for x, z in zip(c, straight):
+        assert np.array_equal(x, z)
+    # a blob of another layout is refused and leaves the state alone
+    small = gpu.Simulation(W.c1(n=64, count=2, storage=storage))
+    before = [t.cpu().numpy() for t in small.fields()]
+    with pytest.raises(gpu.LbpfError) as e:
+        small.load_state(ck)
+    assert e.value.code == -1
+    after = [t.cpu().numpy() for t in small.fields()]
+    assert small.step_count == 0 and all(np.array_equal(x, y) for x, y in zip(before, after))
 
 
 # Four-fold strengths above 1/15 make the stiffness a + a'' negative in some

@@ -1,0 +1,386 @@
+"""Pins of the oracle's set-up and per-entry rules against what the paper and
+the mathematics fix: the seed initial state (Sec. 2, Eq. Initial_Condition and
+Eq. Intial-Cond_u; Sec. 3, Eq. Feq_Phase and Eq. EqFunction_Tempr for the
+initial populations; Sec. 4.3 for the initial crystal index), the FP64
+diagnostics on hand-built fields, the orientation R of an anisotropy entry
+(Sec. 4.3, Eq. As_Multi generalised to 3D rotations) and the checks on entries
+(a_s > 0; symmetry about the mirror planes of a symmetric box, Sec. 5).
+
+Nothing here compares the oracle with itself: expected values are closed
+forms, geometric counts, exact moment identities, equilibrium properties of
+the model's own equation, or invariances.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1606_09432_amd import workloads as W
+
+
+def _lattice_vectors(oracle_mod, name):
+    e, w, _, e2 = oracle_mod.lattice(name)
+    return e.astype(np.float64), w, e2
+
+
+# ---------------------------------------------------------------------------
+# Initial profile (Sec. 2, Eq. Initial_Condition): the steady planar solution
+# of the phase-field equation with u = 0 and a_s = 1 is -tanh(x / (sqrt(2) W0))
+# in physical units, i.e. width sqrt(2) W0 / dx in lattice units.  A seed of
+# enormous radius puts that planar interface in the box; started from the
+# oracle's own initial state, it must stay put.  A profile of another width
+# (sqrt(2 W0) instead of sqrt(2) W0, or W0 not divided by dx) relaxes.
+# ---------------------------------------------------------------------------
+def _planar_seed_cfg(W0=2.0, dx=0.4, big=1.0e6, x_front=60.0, n=160):
+    return W.SimConfig(lattice="D2Q9_D2Q5", nx=n, ny=8, nz=1, boundary="zero_flux", gradient="dd",
+                       storage="fp64", W0=W0, tau0=1.0, lam=10.0, kappa=1.0, delta=0.0, dx=dx, dt=0.004,
+                       aniso=[W.Aniso("iso")], seeds=[W.Seed(x_front - big, 4.0, 0.0, big, 1)],
+                       tip_dir=(1, 0, 0))
+
+
+def _drift(oracle_mod, cfg, steps, phi0=None):
+    sim = oracle_mod.OracleSim(cfg)
+    if phi0 is not None:
+        sim.set_fields(phi0, np.zeros_like(phi0))
+    start = sim.phi().copy()
+    sim.step(steps)
+    return np.abs(sim.phi() - start).max(), start
+
+
+def test_initial_profile_is_the_planar_equilibrium(oracle_mod):
+    cfg = _planar_seed_cfg()
+    drift, start = _drift(oracle_mod, cfg, 300)
+    # the start crosses zero at the front and saturates on both sides
+    row = start[4]
+    assert row[59] > 0 > row[61] and row[0] > 0.999 and row[-1] < -0.999
+    x = np.arange(cfg.nx)
+    w_ok = math.sqrt(2.0) * cfg.W0 / cfg.dx
+    drifts = {}
+    for name, w in [("sqrt(2 W0)/dx", math.sqrt(2.0 * cfg.W0) / cfg.dx), ("sqrt(2) W0", math.sqrt(2.0) * cfg.W0)]:
+        wrong = np.tanh((60.0 - x) / w)[None, :].repeat(cfg.ny, 0)
+        drifts[name] = _drift(oracle_mod, cfg, 300, wrong)[0]
+    ref = np.tanh((60.0 - x) / w_ok)[None, :].repeat(cfg.ny, 0)
+    drift_ref = _drift(oracle_mod, cfg, 300, ref)[0]
+    # the seeded start is the planar tanh of width sqrt(2) W0 / dx (the far
+    # centre bends the front by < 1e-4 lu); it relaxes only by the lattice's own
+    # small departure from tanh (6e-3 in 300 steps at dx/W0 = 0.2), a tenth or
+    # less of what a profile of either wrong width does (0.10 and 0.28)
+    assert np.abs(start - ref).max() < 1e-4
+    assert drift < 1e-2 and abs(drift - drift_ref) < 1e-4, (drift, drift_ref)
+    for name, d in drifts.items():
+        assert d > 10 * drift, (name, d, drift)
+
+
+def test_initial_zero_crossing_is_the_seed_radius(oracle_mod):
+    """The phi = 0 level of a seed is the sphere of radius R (tanh vanishes at
+    d = R): the interpolated tip along the axes, a face diagonal and a body
+    diagonal sits at R up to the linear interpolation of tanh between nodes."""
+    R = 7.3
+    for tip_dir, tol in [((1, 0, 0), 0.005), ((1, 1, 0), 0.02), ((1, 1, 1), 0.02)]:
+        cfg = W.small_3d(n=33, radius=R).replace(tip_dir=tip_dir)
+        sim = oracle_mod.OracleSim(cfg)
+        d = sim.diagnostics()
+        assert abs(d["tip_position"] - R) < tol, (tip_dir, d["tip_position"])
+
+
+def _overlap_cfg(ids=True):
+    return W.SimConfig(lattice="D3Q19_D3Q7", nx=30, ny=26, nz=24, boundary="zero_flux", gradient="dd",
+                       storage="fp64", delta=0.4, kappa=W.KAPPA_C0,
+                       aniso=[W.Aniso("iso"), W.Aniso("cubic", eps=0.05), W.Aniso("cubic", eps=0.03)],
+                       seeds=[W.Seed(11.2, 12.1, 11.7, 6.4, 1), W.Seed(18.6, 13.3, 12.4, 5.13, 2)],
+                       use_ids=ids, tip_dir=(1, 0, 0), xi=0.01)
+
+
+def _seed_distances(cfg):
+    z, y, x = np.meshgrid(*[np.arange(n) for n in cfg.shape], indexing="ij")
+    return [np.sqrt((x - s.x) ** 2 + (y - s.y) ** 2 + (z - s.z) ** 2) - s.radius for s in cfg.seeds]
+
+
+def test_overlapping_seeds_form_their_union(oracle_mod):
+    """Several seeds combine by pointwise maximum (the union of the crystals):
+    phi > 0 exactly on the lattice nodes inside at least one sphere, counted
+    here by brute force; the minimum would leave only the intersection."""
+    cfg = _overlap_cfg()
+    gap1, gap2 = _seed_distances(cfg)
+    assert min(np.abs(gap1).min(), np.abs(gap2).min()) > 1e-3  # no node on a sphere
+    inside_any = (gap1 < 0) | (gap2 < 0)
+    inside_both = (gap1 < 0) & (gap2 < 0)
+    assert inside_both.sum() > 50 and inside_any.sum() > inside_both.sum() + 500
+    sim = oracle_mod.OracleSim(cfg)
+    phi = sim.phi()
+    assert np.array_equal(phi > 0, inside_any)
+    assert sim.diagnostics()["n_solid"] == inside_any.sum()
+
+
+def test_initial_undercooling(oracle_mod):
+    """u = -Delta everywhere at t = 0 (Eq. Intial-Cond_u)."""
+    cfg = _overlap_cfg()
+    sim = oracle_mod.OracleSim(cfg)
+    assert np.all(sim.u() == -cfg.delta)
+    assert abs(sim.diagnostics()["sum_u"] + cfg.delta * cfg.nodes) < 1e-9 * cfg.nodes
+
+
+def test_initial_crystal_index(oracle_mod):
+    """Sec. 4.3: a node inside exactly one crystal carries its index, a liquid
+    node whose gradient is below the threshold xi carries 0, and a liquid node
+    of the diffuse halo (gradient above xi) takes the crystal whose surface is
+    nearer (checked where the two gaps differ by more than one node)."""
+    cfg = _overlap_cfg()
+    sim = oracle_mod.OracleSim(cfg)
+    ids = sim.ids()
+    gap1, gap2 = _seed_distances(cfg)
+    only1 = (gap1 < -0.5) & (gap2 > 0.5)
+    only2 = (gap2 < -0.5) & (gap1 > 0.5)
+    assert only1.sum() > 100 and only2.sum() > 100
+    assert np.all(ids[only1] == 1) and np.all(ids[only2] == 2)
+    p = sim.params()["p"]
+    pmag = np.sqrt((p ** 2).sum(-1))
+    liquid = sim.phi() <= 0.0
+    flat = liquid & (pmag < 0.9 * cfg.xi)
+    assert flat.sum() > 100 and np.all(ids[flat] == 0)
+    halo = liquid & (pmag > 1.1 * cfg.xi)
+    assert halo.sum() > 100 and np.all(ids[halo] != 0)
+    near1 = halo & (gap1 < gap2 - 1.0)
+    near2 = halo & (gap2 < gap1 - 1.0)
+    assert near1.sum() > 20 and near2.sum() > 20
+    assert np.all(ids[near1] == 1) and np.all(ids[near2] == 2)
+    # without the index field every node reads 0
+    assert np.all(oracle_mod.OracleSim(_overlap_cfg(ids=False)).ids() == 0)
+
+
+@pytest.mark.parametrize("lattice", ["D2Q9_D2Q5", "D3Q19_D3Q7", "D3Q15_D3Q7"])
+def test_initial_populations_are_equilibria(oracle_mod, lattice):
+    """g starts at g^(0)(phi, N) of Eq. Feq_Phase: its moments are phi,
+    -Dphi N and e^2 phi I (Sec. 3.2, the moment equations of g^(0)), with N the
+    flux of the initial phi; f starts at w_i u (Eq. EqFunction_Tempr)."""
+    if lattice == "D2Q9_D2Q5":
+        cfg = W.c0(n=40).replace(boundary="zero_flux", seeds=[W.Seed(17.3, 21.6, 0, 6.2, 1)],
+                                 aniso=[W.Aniso("sectoral", 0.05, 4, 0.3)])
+        pname, uname = "D2Q9", "D2Q5"
+    else:
+        cfg = W.small_3d(n=22, radius=5.2, aniso=W.Aniso("cubic_hak", eps=0.1)).replace(lattice=lattice)
+        cfg.seeds[0].x = 10.4
+        pname, uname = ("D3Q15" if lattice == "D3Q15_D3Q7" else "D3Q19"), "D3Q7"
+    sim = oracle_mod.OracleSim(cfg)
+    g, f, phi, u = sim.g(), sim.f(), sim.phi(), sim.u()
+    e, w, e2 = _lattice_vectors(oracle_mod, pname)
+    Nf = sim.params()["N"]
+    Dphi = cfg.W0 ** 2 * cfg.dt / (cfg.tau0 * cfg.dx ** 2)
+    assert np.abs(Nf).max() > 1e-3  # the interface carries a flux
+    gm = np.moveaxis(g, 0, -1)  # [..., q]
+    np.testing.assert_allclose(gm.sum(-1), phi, rtol=0, atol=1e-15)
+    for a in range(3):
+        np.testing.assert_allclose(gm @ e[:, a], -Dphi * Nf[..., a], rtol=0, atol=1e-15)
+        for b in range(3):
+            expect = (e2 * phi) if (a == b and (a < 2 or cfg.dim == 3)) else 0.0 * phi
+            np.testing.assert_allclose(gm @ (e[:, a] * e[:, b]), expect, rtol=0, atol=1e-15)
+    eu, wu, _ = _lattice_vectors(oracle_mod, uname)
+    np.testing.assert_allclose(np.moveaxis(f, 0, -1), u[..., None] * wu, rtol=0, atol=0)
+    assert np.all(u == -cfg.delta)
+
+
+# ---------------------------------------------------------------------------
+# FP64 diagnostics on hand-built fields whose sums are exact in binary.
+# ---------------------------------------------------------------------------
+def test_diagnostics_on_hand_built_fields(oracle_mod):
+    cfg = W.small_3d(n=12).replace(seeds=[W.Seed(3, 4, 5, 2.0, 1)])
+    sim = oracle_mod.OracleSim(cfg)
+    rng = np.random.default_rng(11)
+    phi = rng.choice([-1.0, -0.5, 0.0, 0.25, 1.0], size=cfg.shape)
+    u = rng.choice([-0.5, 0.125, 0.375], size=cfg.shape)
+    sim.set_fields(phi, u)
+    d = sim.diagnostics()
+    # every partial sum is a multiple of 1/8 below 2^40: exact in any order
+    assert d["sum_phi"] == float(phi.sum())
+    assert d["sum_u"] == float(u.sum())
+    assert d["sum_u_minus_half_phi"] == float((u - 0.5 * phi).sum())
+    assert d["n_solid"] == float((phi > 0).sum())
+    assert d["solid_fraction"] == float((1.0 + phi).sum()) / (2.0 * cfg.nodes)
+    assert d["nonfinite"] == 0.0
+    phi[7, 2, 9] = np.nan
+    sim.set_fields(phi, u)
+    assert sim.diagnostics()["nonfinite"] == 1.0
+    phi[7, 2, 9] = 0.0
+    u[1, 1, 1] = np.inf
+    sim.set_fields(phi, u)
+    assert sim.diagnostics()["nonfinite"] == 1.0
+
+
+# ---------------------------------------------------------------------------
+# Orientation of an entry: a(n) = A(R n) (Sec. 4.3, Eq. As_Multi generalised).
+# ---------------------------------------------------------------------------
+def _rz(t):
+    c, s = math.cos(t), math.sin(t)
+    return (c, -s, 0.0, s, c, 0.0, 0.0, 0.0, 1.0)
+
+
+GENERIC_R = W.rotation((1.0, 2.0, 3.0), 0.7)
+
+
+def test_sectoral_angle_is_a_rotation_about_z(oracle_mod):
+    """Eq. As_Theta: the angle phi0 of a sectoral entry turns the crystal about
+    z; the same entry with phi0 = 0 and R = rotation about z by -phi0 gives the
+    same a_s and N."""
+    rng = np.random.default_rng(5)
+    for q, t in [(4, 0.35), (6, 1.1), (5, -0.4)]:
+        ang = W.Aniso("sectoral", eps=0.05, q=q, phi0=t)
+        rot = W.Aniso("sectoral", eps=0.05, q=q, phi0=0.0, R=_rz(-t))
+        for _ in range(30):
+            p = rng.normal(size=3) * 0.3
+            if q != 6:
+                p[2] = 0.0
+            a1, N1 = oracle_mod.flux(ang, p)
+            a2, N2 = oracle_mod.flux(rot, p)
+            assert abs(a1 - a2) < 1e-14
+            np.testing.assert_allclose(N1, N2, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("entry,vals", [
+    (W.Aniso("cubic", eps=0.05), {"100": 1.05, "110": 0.95, "111": 1 - 0.05 * 5 / 3}),
+    (W.Aniso("cubic_hak", eps=0.1, gamma=0.0), {"100": 1.04, "110": 0.99, "111": 1 + 0.1 * (1 / 3 - 0.6)}),
+    (W.Aniso("cubic_s", gamma=0.02), {"100": 1.0, "110": 1.0, "111": 1 + 66 * 0.02 / 27}),
+])
+def test_rotated_entry_moves_its_growth_directions(oracle_mod, entry, vals):
+    """With R, the value the unrotated entry takes on a lattice direction e
+    (closed forms: Q = 1, 1/2, 1/3 and S = 0, 0, 1/27 on <100>, <110>, <111>)
+    is taken on R^T e."""
+    R = np.array(GENERIC_R).reshape(3, 3)
+    rot = W.Aniso(entry.kind, eps=entry.eps, gamma=entry.gamma, R=GENERIC_R)
+    dirs = {"100": np.array([1.0, 0, 0]), "110": np.array([1.0, 1, 0]) / math.sqrt(2),
+            "111": np.array([1.0, 1, 1]) / math.sqrt(3)}
+    for k, e in dirs.items():
+        a, _ = oracle_mod.aniso_eval(rot, R.T @ e)
+        assert abs(a - vals[k]) < 1e-14, (k, a)
+        a0, _ = oracle_mod.aniso_eval(rot, e)
+        if k == "100":
+            assert abs(a0 - vals[k]) > 1e-4  # the lattice axis is no longer a crystal axis
+
+
+@pytest.mark.parametrize("entry", [W.Aniso("cubic_hak", eps=0.1, R=GENERIC_R),
+                                   W.Aniso("cubic_s", gamma=0.02, R=W.rotation((0.0, 1.0, 1.0), 0.5)),
+                                   W.Aniso("sectoral", eps=0.05, q=6, R=W.rotation((1.0, 0.0, 0.2), 0.9))])
+def test_rotated_flux_orthogonal_and_matches_finite_difference(oracle_mod, entry):
+    """N = |p|^2 a da/dp (Eq. TermesAnisotropes) and p . N = 0 for rotated entries."""
+    rng = np.random.default_rng(60)
+    for _ in range(20):
+        p = rng.normal(size=3) * rng.uniform(0.01, 0.5)
+        a, N = oracle_mod.flux(entry, p)
+        assert abs(p @ N) <= 1e-14 * np.linalg.norm(p) * max(np.linalg.norm(N), 1e-300) + 1e-18
+        h = 1e-6 * np.linalg.norm(p)
+        grad = np.array([(oracle_mod.flux(entry, p + h * ei)[0] - oracle_mod.flux(entry, p - h * ei)[0]) / (2 * h)
+                         for ei in np.eye(3)])
+        np.testing.assert_allclose(N, (p @ p) * a * grad, rtol=0, atol=1e-8)
+
+
+def test_lattice_symmetry_rotation_leaves_cubic_entries_unchanged(oracle_mod):
+    """A rotation that maps the lattice onto itself (90 degrees about z, or the
+    cyclic permutation of the axes) is a symmetry of every cubic harmonic."""
+    rng = np.random.default_rng(9)
+    for R in [_rz(math.pi / 2), (0.0, 0.0, 1.0, 1.0, 0.0, 0.0, 0.0, 1.0, 0.0)]:
+        for base in [W.Aniso("cubic", eps=0.05), W.Aniso("cubic_hak", eps=0.1, gamma=-0.02), W.Aniso("cubic_s", gamma=0.02)]:
+            rot = W.Aniso(base.kind, eps=base.eps, gamma=base.gamma, R=tuple(float(round(v)) for v in R))
+            for _ in range(20):
+                p = rng.normal(size=3)
+                a1, N1 = oracle_mod.flux(base, p)
+                a2, N2 = oracle_mod.flux(rot, p)
+                assert abs(a1 - a2) < 1e-15
+                np.testing.assert_allclose(N1, N2, rtol=0, atol=1e-14 * np.linalg.norm(p))
+
+
+@pytest.mark.parametrize("lattice", ["D3Q19_D3Q7", "D3Q15_D3Q7"])
+def test_whole_step_covariance_under_rotation(oracle_mod, lattice):
+    """Turning the crystal (entry R0 -> R0 P^T) and the seeds by the same
+    lattice rotation P (90 degrees about z through the box centre) turns the
+    solution: phi_B(P x) = phi_A(x) (the gradient turns with the field, and
+    A(R0 P^T P n) = A(R0 n))."""
+    n, c = 25, 12
+    R0 = np.array(GENERIC_R).reshape(3, 3)
+    P = np.array(_rz(math.pi / 2)).reshape(3, 3).round()
+    seeds_a = [W.Seed(9.3, 11.4, 12.6, 5.0, 1)]
+
+    def turn(s):
+        v = P @ np.array([s.x - c, s.y - c, s.z - c]) + c
+        return W.Seed(float(v[0]), float(v[1]), float(v[2]), s.radius, s.id)
+
+    base = W.small_3d(n=n, radius=5.0).replace(lattice=lattice)
+    cfg_a = base.replace(aniso=[W.Aniso("cubic_hak", eps=0.1, R=tuple(R0.ravel()))], seeds=seeds_a)
+    cfg_b = base.replace(aniso=[W.Aniso("cubic_hak", eps=0.1, R=tuple((R0 @ P.T).ravel()))],
+                         seeds=[turn(s) for s in seeds_a])
+    A = oracle_mod.OracleSim(cfg_a)
+    B = oracle_mod.OracleSim(cfg_b)
+    A.step(30)
+    B.step(30)
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    # P maps (x, y) -> (2c - y, x) about the centre: node (x, y, z) of A is node (2c - y, x, z) of B
+    for fa, fb in [(A.phi(), B.phi()), (A.u(), B.u())]:
+        np.testing.assert_allclose(fb[z, x, 2 * c - y], fa, rtol=0, atol=1e-12)
+    # and the rotation matters: the unturned entry on the turned seeds differs
+    C = oracle_mod.OracleSim(cfg_b.replace(aniso=cfg_a.aniso))
+    C.step(30)
+    assert np.abs(C.phi()[z, x, 2 * c - y] - A.phi()).max() > 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Checks on entries: a_s > 0, and symmetry about the mirror planes.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("entry,dim,lo", [
+    (W.Aniso("cubic", eps=0.05), 3, 1 - 0.05 * 5 / 3),           # Q = 1/3 on <111>
+    (W.Aniso("cubic", eps=-0.04), 3, 1 - 0.04),                  # Q = 1 on <100>
+    (W.Aniso("cubic_hak", eps=0.1, gamma=0.0), 3, 1 + 0.1 * (1 / 3 - 0.6)),
+    (W.Aniso("cubic_s", gamma=-0.3), 3, 1 - 66 * 0.3 / 27),      # S = 1/27 on <111>
+    (W.Aniso("sectoral", eps=0.05, q=4), 2, 0.95),               # cos 4 phi = -1 on the diagonals
+    (W.Aniso("cubic", eps=0.05, R=GENERIC_R), 3, None),
+])
+def test_entry_minimum_closed_forms(oracle_mod, entry, dim, lo):
+    """The smallest a_s over the checked directions is the closed-form minimum,
+    reached on a lattice direction; a rotation does not change it (up to the
+    directions sampled)."""
+    m = oracle_mod.aniso_min(entry, dim)
+    if lo is None:
+        lo = oracle_mod.aniso_min(W.Aniso(entry.kind, eps=entry.eps, gamma=entry.gamma), dim)
+        assert lo <= m < lo + 1e-3
+    else:
+        assert abs(m - lo) < 1e-14, (m, lo)
+
+
+@pytest.mark.parametrize("entry,dim", [(W.Aniso("sectoral", eps=1.2, q=4), 2), (W.Aniso("cubic", eps=0.7), 3),
+                                       (W.Aniso("cubic_s", gamma=-0.5), 3),
+                                       (W.Aniso("cubic_hak", eps=0.0, gamma=1.2), 3)])
+def test_entries_with_nonpositive_anisotropy_are_refused(oracle_mod, entry, dim):
+    assert oracle_mod.aniso_min(entry, dim) <= 0.0
+    cfg = W.c0(n=16) if dim == 2 else W.small_3d(n=8)
+    with pytest.raises(ValueError) as e:
+        oracle_mod.OracleSim(cfg.replace(aniso=[entry]))
+    assert e.value.code == -2
+    ok = W.Aniso(entry.kind, eps=0.55 if entry.kind == "cubic" else 0.05, q=entry.q, gamma=0.0)
+    oracle_mod.OracleSim(cfg.replace(aniso=[ok]))  # a_s min 1 - 5 (0.55) / 3 > 0: accepted
+
+
+SYMMETRIC = [W.Aniso("cubic", eps=0.05), W.Aniso("cubic_hak", eps=0.1, gamma=-0.02), W.Aniso("cubic_s", gamma=0.02),
+             W.Aniso("sectoral", eps=0.05, q=4), W.Aniso("sectoral", eps=0.05, q=6),
+             W.Aniso("cubic", eps=0.05, R=_rz(math.pi / 4))]
+ASYMMETRIC = [W.Aniso("sectoral", eps=0.05, q=6, phi0=0.3), W.Aniso("sectoral", eps=0.05, q=4, phi0=0.2),
+              W.Aniso("cubic", eps=0.05, R=GENERIC_R), W.Aniso("sectoral", eps=0.05, q=3)]
+
+
+@pytest.mark.parametrize("k", range(len(SYMMETRIC)))
+def test_symmetric_entries_pass_the_mirror_check(oracle_mod, k):
+    e = SYMMETRIC[k]
+    assert oracle_mod.aniso_mirror_symmetric(e, 3)
+    cfg = W.small_3d(n=10, aniso=e).replace(boundary="mirror_low", seeds=[W.Seed(0, 0, 0, 3.0, 1)])
+    oracle_mod.OracleSim(cfg)
+
+
+@pytest.mark.parametrize("k", range(len(ASYMMETRIC)))
+def test_asymmetric_entries_are_refused_in_mirror_boxes(oracle_mod, k):
+    """An octant stands for the symmetric domain only if a_s is (Sec. 5): an
+    entry that is not symmetric about the planes is refused there (-6) and
+    accepted with walls.  cos q(phi - phi0) with phi0 = 0.3, or odd q, changes
+    under n_x -> -n_x; a generic rotation breaks the cubic symmetry."""
+    e = ASYMMETRIC[k]
+    assert not oracle_mod.aniso_mirror_symmetric(e, 3)
+    cfg = W.small_3d(n=10, aniso=e).replace(seeds=[W.Seed(0, 0, 0, 3.0, 1)])
+    oracle_mod.OracleSim(cfg)
+    with pytest.raises(ValueError) as err:
+        oracle_mod.OracleSim(cfg.replace(boundary="mirror_low"))
+    assert err.value.code == -6
