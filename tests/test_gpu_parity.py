@@ -175,7 +175,8 @@ def test_initial_state_parity(gpu, oracle_mod, which):
             assert np.array_equal(ids, orc.ids())
             assert len(np.unique(ids)) == len(cfg.seeds) + 1
         if steps == 0:
-            assert np.all(u == -cfg.delta)
+            # u is read back as the sum of its populations w_i u
+            assert np.abs(u + cfg.delta).max() <= 1e-15
             sim.step(1)
             orc.step(1)
 
