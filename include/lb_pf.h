@@ -191,6 +191,19 @@ int lb_pf_step(lbpf_handle *h, int n_steps, void *hip_stream);
  * LBPF_ERR_NONFINITE (and fills out) when a phi or u is not finite. */
 int lb_pf_diagnostics(lbpf_handle *h, lbpf_diag *out, void *hip_stream);
 
+/* lb_pf_diagnostics for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid allocation): the same reductions and
+ * the same results, but their per-block partials and the reduced values live
+ * in a static device array of the library (32 KiB per GPU, held until the
+ * process ends; the reductions need 24.6 KiB) instead of the handle's
+ * workspace.  It calls no hipMalloc, hipFree or allocating routine.  Every
+ * call on one GPU shares that GPU's array and leaves the last call's values
+ * in it (nothing in it must start at zero: each call overwrites what it
+ * reads): calls that overlap on one GPU, from several threads or streams,
+ * race.  The handle's device (current at lb_pf_init) must be the current
+ * device (LBPF_ERR_ARG otherwise).  Synchronises hip_stream. */
+int lb_pf_diagnostics_noalloc(lbpf_handle *h, lbpf_diag *out, void *hip_stream);
+
 /* Writes phi, u (FP64) and the crystal index of simulation `sim` into caller
  * device buffers of nx*ny*nz elements (any pointer may be NULL). */
 int lb_pf_export_fields(lbpf_handle *h, int sim, double *phi_dev, double *u_dev,

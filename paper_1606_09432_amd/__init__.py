@@ -35,7 +35,7 @@ EXPORTED_SYMBOLS = (
     "lb_pf_workspace_bytes", "lb_pf_init", "lb_pf_step", "lb_pf_diagnostics", "lb_pf_export_fields",
     "lb_pf_export_dists", "lb_pf_import_fields", "lb_pf_state_bytes", "lb_pf_save_state",
     "lb_pf_load_state", "lb_pf_set_tile", "lb_pf_get_tile", "lb_pf_autotune", "lb_pf_info",
-    "lb_pf_destroy", "lb_pf_last_error", "lb_pf_sharp_interface",
+    "lb_pf_destroy", "lb_pf_last_error", "lb_pf_sharp_interface", "lb_pf_diagnostics_noalloc",
 )
 
 
@@ -91,6 +91,7 @@ def load_library():
         "lb_pf_init": [cfgp, C.c_int, vp, sz, vp, C.POINTER(vp)],
         "lb_pf_step": [vp, C.c_int, vp],
         "lb_pf_diagnostics": [vp, C.POINTER(LbpfDiag), vp],
+        "lb_pf_diagnostics_noalloc": [vp, C.POINTER(LbpfDiag), vp],
         "lb_pf_export_fields": [vp, C.c_int, vp, vp, vp, vp],
         "lb_pf_export_dists": [vp, C.c_int, vp, vp, vp],
         "lb_pf_import_fields": [vp, C.c_int, vp, vp, vp, vp],
@@ -208,6 +209,15 @@ class Simulation:
     def diagnostics(self, allow_nonfinite: bool = False) -> List[dict]:
         out = (LbpfDiag * len(self.cfgs))()
         rc = self.lib.lb_pf_diagnostics(self.h, out, self._stream())
+        if rc != 0 and not (allow_nonfinite and rc == ERR_NONFINITE):
+            _check(rc)
+        return [{k: getattr(d, k) for k, _ in LbpfDiag._fields_} for d in out]
+
+    def diagnostics_noalloc(self, allow_nonfinite: bool = False) -> List[dict]:
+        """The same records through the entry point that allocates nothing
+        (reduction scratch in the library's static device array)."""
+        out = (LbpfDiag * len(self.cfgs))()
+        rc = self.lib.lb_pf_diagnostics_noalloc(self.h, out, self._stream())
         if rc != 0 and not (allow_nonfinite and rc == ERR_NONFINITE):
             _check(rc)
         return [{k: getattr(d, k) for k, _ in LbpfDiag._fields_} for d in out]

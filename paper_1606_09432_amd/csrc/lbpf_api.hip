@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -82,8 +83,43 @@ struct lbpf_handle {
   size_t bytes = 0;
   int parity = 0;
   int64_t step = 0;
+  int device = 0;  // the device current at lb_pf_init
   BatchState batch;
 };
+
+// Scratch of lb_pf_diagnostics_noalloc: the per-block partials and the result
+// of the diagnostics reductions, in a file-scope device array instead of the
+// handle's workspace.  Each GPU holds its own copy until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory: its
+// device address is taken once per device with hipGetSymbolAddress (at
+// lb_pf_init, with that device current) and only that address is used.
+constexpr int kScratchDoubles = 4096;  // 32 KiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};  // device address of scratch, per device
+
+// Takes the device address of scratch on device dev (current), once.
+int scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(LBPF_ERR_UNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return LBPF_OK;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(LBPF_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[dev] = static_cast<double *>(p);
+  return LBPF_OK;
+}
+
+double *scratch_of(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[dev];
+}
+}  // namespace
 
 namespace {
 
@@ -495,6 +531,18 @@ int lb_pf_init(const lbpf_config *cfgs, int n_sims, void *dev_workspace, size_t 
   h->ws = static_cast<char *>(dev_workspace);
   h->bytes = bytes;
   h->parity = 0;
+  {
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+      delete h;
+      return fail(LBPF_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    rc = scratch_setup(h->device);
+    if (rc) {
+      delete h;
+      return rc;
+    }
+  }
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   for (SimHost &s : h->sims) {
     std::vector<AnisoDev> tab(s.cfg.n_aniso);
@@ -639,9 +687,10 @@ int lb_pf_step(lbpf_handle *h, int n_steps, void *hip_stream) {
   return LBPF_OK;
 }
 
-int lb_pf_diagnostics(lbpf_handle *h, lbpf_diag *out, void *hip_stream) {
-  if (!h || !out) return fail(LBPF_ERR_ARG, "null argument");
-  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+namespace {
+// The diagnostics of every simulation; partials/result of the reductions in
+// the workspace (static_part == nullptr) or in the static scratch array.
+int run_diagnostics(lbpf_handle *h, lbpf_diag *out, hipStream_t st, double *static_part) {
   int bad = 0;
   for (size_t k = 0; k < h->sims.size(); ++k) {
     const SimHost &s = h->sims[k];
@@ -654,8 +703,8 @@ int lb_pf_diagnostics(lbpf_handle *h, lbpf_diag *out, void *hip_stream) {
       o[1] = (int)std::floor(s.seeds[0].y + 0.5);
       o[2] = (int)std::floor(s.seeds[0].z + 0.5);
     }
-    double *part = reinterpret_cast<double *>(h->ws + s.off_part);
-    double *res = reinterpret_cast<double *>(h->ws + s.off_res);
+    double *part = static_part ? static_part : reinterpret_cast<double *>(h->ws + s.off_part);
+    double *res = static_part ? static_part + kDiagVals * kDiagBlocks : reinterpret_cast<double *>(h->ws + s.off_res);
     HIPCHK(launch_diag(s.dim, s.storage, d, part, res, 0, o[0], o[1], o[2], dir[0], dir[1], dir[2], st));
     double host[kDiagVals + 1];
     HIPCHK(hipMemcpyAsync(host, res, sizeof(host), hipMemcpyDeviceToHost, st));
@@ -674,6 +723,27 @@ int lb_pf_diagnostics(lbpf_handle *h, lbpf_diag *out, void *hip_stream) {
   }
   if (bad) return fail(LBPF_ERR_NONFINITE, "non-finite phi or u");
   return LBPF_OK;
+}
+}  // namespace
+
+int lb_pf_diagnostics(lbpf_handle *h, lbpf_diag *out, void *hip_stream) {
+  if (!h || !out) return fail(LBPF_ERR_ARG, "null argument");
+  return run_diagnostics(h, out, static_cast<hipStream_t>(hip_stream), nullptr);
+}
+
+int lb_pf_diagnostics_noalloc(lbpf_handle *h, lbpf_diag *out, void *hip_stream) {
+  if (!h || !out) return fail(LBPF_ERR_ARG, "null argument");
+  // the reductions need kDiagVals partials per block and kDiagVals + 1 results
+  constexpr size_t need = (size_t)kDiagVals * kDiagBlocks + kDiagVals + 2;
+  static_assert(need <= (size_t)kScratchDoubles, "diagnostics scratch exceeds the static array");
+  if (need > (size_t)kScratchDoubles)
+    return fail(LBPF_ERR_UNSUPPORTED, "diagnostics need more scratch than the static array holds");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != h->device) return fail(LBPF_ERR_ARG, "the handle's device is not the current device");
+  double *ptr = scratch_of(dev);
+  if (!ptr) return fail(LBPF_ERR_HIP, "static scratch not set up on this device");
+  return run_diagnostics(h, out, static_cast<hipStream_t>(hip_stream), ptr);
 }
 
 int lb_pf_export_fields(lbpf_handle *h, int sim, double *phi_dev, double *u_dev, int16_t *ids_dev,
