@@ -68,13 +68,41 @@ def measured_traffic(lattice: str, storage: str):
     return ent.get("bytes_per_launch")
 
 
-def run_gpu(cfg, steps: int, warmup: int, autotune: bool):
+def time_stream_copy(sim, reps: int = 5):
+    """The plain streaming copy of the simulation's current state block into
+    its other block (the step's own buffers): every state byte read once and
+    written once, as the step must.  Returns (ms per copy, bytes moved)."""
     import torch
 
     import paper_1606_09432_amd as lb
 
-    print(f"[bench] {cfg.storage}: init {cfg.nx}x{cfg.ny}x{cfg.nz}", file=sys.stderr, flush=True)
+    src, nbytes = sim.state_block()
+    other = src + nbytes if src + nbytes + nbytes <= sim.workspace.data_ptr() + sim.workspace.numel() else None
+    if other is None:
+        return None, 0
+    stream = torch.cuda.current_stream()
+    lb.stream_copy(src, other, nbytes)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        lb.stream_copy(src, other, nbytes)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, 2 * nbytes
+
+
+def run_gpu(cfg, steps: int, warmup: int, autotune: bool, copy_ceiling: bool = False, pre_steps: int = 0):
+    import torch
+
+    import paper_1606_09432_amd as lb
+
+    print(f"[bench] {cfg.storage}: init {cfg.nx}x{cfg.ny}x{cfg.nz} ({len(cfg.seeds)} seeds)", file=sys.stderr,
+          flush=True)
     sim = lb.Simulation(cfg)
+    if pre_steps:
+        sim.step(pre_steps)
     if autotune:
         sim.autotune(2)
     stream = torch.cuda.current_stream()
@@ -89,6 +117,20 @@ def run_gpu(cfg, steps: int, warmup: int, autotune: bool):
     ms = e0.elapsed_time(e1)
     diag = sim.diagnostics()[0]
     tile = sim.get_tile()
+    aniso_frac = anisotropic_fraction(sim) if cfg.nodes <= 512 ** 3 else None
+    copy = None
+    if copy_ceiling:
+        # the step's parity is even after an even number of steps: the state
+        # block read next is the first, and the copy writes the second
+        if sim.step_count % 2:
+            sim.step(1)
+        cms, cbytes = time_stream_copy(sim)
+        if cms:
+            copy = {"ms": cms, "bytes": cbytes, "GBps": cbytes / (cms * 1e-3) / 1e9,
+                    "kind": "lb_pf_stream_copy of the state block into the other block (16-byte nontemporal "
+                            "vectors), read + written bytes"}
+            print(f"[bench] {cfg.storage}: state-block copy {cbytes / 1e9:.2f} GB in {cms:.3f} ms, "
+                  f"{copy['GBps']:.0f} GB/s", file=sys.stderr, flush=True)
     del sim
     torch.cuda.empty_cache()
     nodes = cfg.nodes
@@ -105,7 +147,32 @@ def run_gpu(cfg, steps: int, warmup: int, autotune: bool):
                      "bytes_per_node_step": b_alg},
         "diag": {"tip_position": diag["tip_position"], "solid_fraction": diag["solid_fraction"],
                  "nonfinite": diag["nonfinite"]},
+        "copy": copy, "anisotropic_fraction": aniso_frac,
     }
+
+
+def anisotropic_fraction(sim) -> float:
+    """Share of nodes whose phi gradient exceeds the isotropic cutoff
+    |p| > 1e-8 (lattice units), i.e. that evaluate a_s and N in the step.  The
+    gradient is taken here by central differences of the exported phi (a
+    measurement of the state, not the step's own gradient)."""
+    import torch
+
+    phi = sim.fields()[0]
+    if phi.dim() == 2:
+        phi = phi.unsqueeze(0)
+    p2 = torch.zeros(phi.shape[1:], dtype=torch.float64, device=phi.device)
+    count = 0
+    for k in range(phi.shape[0]):  # one plane at a time keeps the memory small
+        zl, zh = max(k - 1, 0), min(k + 1, phi.shape[0] - 1)
+        p2.zero_()
+        if phi.shape[0] > 1:
+            p2 += ((phi[zh] - phi[zl]) / max(zh - zl, 1)) ** 2
+        gy, gx = torch.gradient(phi[k])
+        p2 += gx * gx + gy * gy
+        count += int((p2 > 1e-16).sum())
+    del phi
+    return count / sim.nodes()
 
 
 def run_batched(steps: int, warmup: int):
@@ -619,6 +686,7 @@ def main():
     ap.add_argument("--only", choices=["fp16", "fp64", "fp32"], default=None)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 2D ensemble")
     ap.add_argument("--no-d3q15", action="store_true", help="skip the D3Q15 runs")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense-interface 512^3 runs")
     ap.add_argument("--accuracy", choices=["c2", "c3"], default=None,
                     help="only report the FP32/FP16-offset error against FP64 over a run")
     ap.add_argument("--paper3d", action="store_true",
@@ -719,7 +787,8 @@ def main():
     results = {}
     storages = [args.only] if args.only else ["fp16", "fp64"]
     for st in storages:
-        results[st] = run_gpu(W.c3(st, args.variant, n=args.n), args.steps, args.warmup, args.autotune)
+        results[st] = run_gpu(W.c3(st, args.variant, n=args.n), args.steps, args.warmup, args.autotune,
+                              copy_ceiling=True)
     head = "fp16" if "fp16" in results else storages[0]
     r = results[head]
     out = {
@@ -731,13 +800,25 @@ def main():
                                f"{'FP16-offset storage' if head == 'fp16' else head} (headline)",
                    "grid": [args.n] * 3, "storage": head, "tile_y_chunk": r["tile"]},
         "roofline": r["roofline"],
+        "stream_copy": r["copy"], "anisotropic_fraction": r["anisotropic_fraction"],
     }
     for st, rr in results.items():
         if st != head:
             out[st] = {"value": rr["value"], "unit": "MLUPS", "ms_per_step": rr["ms_per_step"],
-                       "dtype": "f64" if st == "fp64" else "f32", "roofline": rr["roofline"], "tile_y_chunk": rr["tile"]}
+                       "dtype": "f64" if st == "fp64" else "f32", "roofline": rr["roofline"], "tile_y_chunk": rr["tile"],
+                       "stream_copy": rr["copy"]}
     if "fp64" in results and "fp16" in results:
         out["fp16_over_fp64"] = results["fp16"]["value"] / results["fp64"]["value"]
+    if not args.no_dense and not args.only:
+        # a state where nearly every node is at an interface (512 crystals)
+        dsteps = min(args.steps, 200)
+        out["dense"] = {"workload": f"{args.n}^3, a crystal every 64 nodes (512 seeds R=20, jittered), "
+                                    f"Eq. As_MatSci <100>, Delta=0.6", "steps": dsteps}
+        for st in ("fp16", "fp64"):
+            rr = run_gpu(W.dense_3d(st, n=args.n), dsteps, min(args.warmup, 20), args.autotune)
+            out["dense"][st] = {"value": rr["value"], "unit": "MLUPS", "ms_per_step": rr["ms_per_step"],
+                                "roofline": rr["roofline"], "tile_y_chunk": rr["tile"],
+                                "anisotropic_fraction": rr["anisotropic_fraction"]}
     if not args.no_batched and not args.only:
         out["batched"] = run_batched(args.steps, args.warmup)
     if not args.no_d3q15 and not args.only:

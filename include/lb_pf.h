@@ -240,6 +240,19 @@ int lb_pf_set_tile(lbpf_handle *h, int tile_y, int chunk);
 int lb_pf_get_tile(const lbpf_handle *h, int *tile_y, int *chunk);
 int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream);
 
+/* Measurement helpers (Sec. 5 measures the cost of a step; these give the
+ * ceiling a step is measured against).  lb_pf_stream_copy reads every byte of
+ * src once and writes it to dst once with 16-byte nontemporal vector
+ * accesses, from a grid of blocks_per_cu (1..64) work-groups of 256 threads
+ * per compute unit: the plain streaming copy that bounds any step moving the
+ * same bytes.  Both buffers are caller-owned device memory, 16-byte aligned
+ * and disjoint; enqueued on hip_stream.  lb_pf_state_ptr returns the device
+ * address and size of simulation `sim`'s current state block inside the
+ * workspace (the bytes a step reads; the step writes as many to the other
+ * block), owned by the handle's caller. */
+int lb_pf_stream_copy(const void *src_dev, void *dst_dev, size_t bytes, int blocks_per_cu, void *hip_stream);
+int lb_pf_state_ptr(const lbpf_handle *h, int sim, void **state, size_t *bytes);
+
 /* Number of simulations, nodes of simulation `sim`, step counter. */
 int lb_pf_info(const lbpf_handle *h, int sim, int64_t *nodes, int64_t *step, int *q_phi, int *q_u);
 

@@ -36,6 +36,7 @@ EXPORTED_SYMBOLS = (
     "lb_pf_export_dists", "lb_pf_import_fields", "lb_pf_state_bytes", "lb_pf_save_state",
     "lb_pf_load_state", "lb_pf_set_tile", "lb_pf_get_tile", "lb_pf_autotune", "lb_pf_info",
     "lb_pf_destroy", "lb_pf_last_error", "lb_pf_sharp_interface", "lb_pf_diagnostics_noalloc",
+    "lb_pf_stream_copy", "lb_pf_state_ptr",
 )
 
 
@@ -104,6 +105,8 @@ def load_library():
         "lb_pf_info": [vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int),
                        C.POINTER(C.c_int)],
         "lb_pf_destroy": [vp],
+        "lb_pf_stream_copy": [vp, vp, sz, C.c_int, vp],
+        "lb_pf_state_ptr": [vp, C.c_int, C.POINTER(vp), C.POINTER(sz)],
         "lb_pf_sharp_interface": [C.c_double] * 4 + [C.POINTER(C.c_double)] * 3,
     }
     for name, args in sig.items():
@@ -152,6 +155,17 @@ def _to_struct(cfg: SimConfig, keep: list) -> LbpfConfig:
     c.seeds = sd
     c.tip_dir[:] = list(cfg.tip_dir)
     return c
+
+
+def stream_copy(src, dst, nbytes: int, blocks_per_cu: int = 8) -> None:
+    """Plain streaming copy of nbytes between two device buffers (torch
+    tensors or raw device addresses) on the current torch stream."""
+    import torch
+
+    sp = src if isinstance(src, int) else src.data_ptr()
+    dp = dst if isinstance(dst, int) else dst.data_ptr()
+    st = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    _check(load_library().lb_pf_stream_copy(C.c_void_p(sp), C.c_void_p(dp), int(nbytes), int(blocks_per_cu), st))
 
 
 def workspace_bytes(cfgs: Union[SimConfig, Sequence[SimConfig]]) -> int:
@@ -285,6 +299,12 @@ class Simulation:
     def autotune(self, steps_per_trial: int = 3):
         _check(self.lib.lb_pf_autotune(self.h, int(steps_per_trial), self._stream()))
         return self.get_tile()
+
+    def state_block(self, sim: int = 0):
+        """(device address, bytes) of simulation `sim`'s current state block."""
+        p, b = C.c_void_p(), C.c_size_t()
+        _check(self.lib.lb_pf_state_ptr(self.h, sim, C.byref(p), C.byref(b)))
+        return p.value, b.value
 
     @property
     def step_count(self) -> int:

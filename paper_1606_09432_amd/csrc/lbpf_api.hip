@@ -136,8 +136,29 @@ AnisoDev to_dev(const lbpf_aniso &a) {
   d.rot = 0;
   for (int k = 0; k < 9; ++k) {
     d.R[k] = a.R[k];
+    d.Rf[k] = (float)a.R[k];
     if (a.R[k] != 0.0) d.rot = 1;
   }
+  // one polynomial c0 + c1 Q + c2 S for the cubic kinds (Sec. 4.1)
+  if (a.kind == LBPF_ANISO_CUBIC) {
+    d.c0 = 1.0 - 3.0 * a.eps;
+    d.c1 = 4.0 * a.eps;
+    d.c2 = 0.0;
+  } else if (a.kind == LBPF_ANISO_CUBIC_HAK) {
+    d.c0 = 1.0 - 3.0 * a.eps / 5.0 - 17.0 * a.gamma / 7.0;
+    d.c1 = a.eps + 3.0 * a.gamma;
+    d.c2 = 66.0 * a.gamma;
+  } else if (a.kind == LBPF_ANISO_CUBIC_S) {
+    d.c0 = 1.0;
+    d.c1 = 0.0;
+    d.c2 = 66.0 * a.gamma;
+  }
+  d.epsf = (float)d.eps;
+  d.crf = (float)d.cr;
+  d.cif = (float)d.ci;
+  d.c0f = (float)d.c0;
+  d.c1f = (float)d.c1;
+  d.c2f = (float)d.c2;
   return d;
 }
 
@@ -388,6 +409,11 @@ SimDev make_dev(const lbpf_handle *h, const SimHost &s, int in) {
   d.lambda = s.cfg.lambda;
   d.omega_u = s.omega_u;
   d.xi2 = s.cfg.xi * s.cfg.xi;
+  d.kphi_f = (float)d.kphi;
+  d.s_f = (float)d.s;
+  d.lambda_f = (float)d.lambda;
+  d.omega_u_f = (float)d.omega_u;
+  d.xi2_f = (float)d.xi2;
   d.width = s.width;
   d.u0 = -s.cfg.delta;
   d.g_in = A + s.off_g;
@@ -849,6 +875,28 @@ int lb_pf_load_state(lbpf_handle *h, const void *dev_buf, size_t bytes, void *hi
     src += s.state_bytes;
   }
   h->step = hd.step;
+  return LBPF_OK;
+}
+
+int lb_pf_stream_copy(const void *src_dev, void *dst_dev, size_t bytes, int blocks_per_cu, void *hip_stream) {
+  if (!src_dev || !dst_dev) return fail(LBPF_ERR_ARG, "null buffer");
+  if (reinterpret_cast<uintptr_t>(src_dev) % 16 != 0 || reinterpret_cast<uintptr_t>(dst_dev) % 16 != 0)
+    return fail(LBPF_ERR_ARG, "buffers must be 16-byte aligned");
+  if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(LBPF_ERR_ARG, "blocks_per_cu must be 1..64");
+  const char *s = static_cast<const char *>(src_dev);
+  const char *d = static_cast<const char *>(dst_dev);
+  if (s < d + bytes && d < s + bytes) return fail(LBPF_ERR_ARG, "buffers overlap");
+  if (bytes == 0) return LBPF_OK;
+  HIPCHK(launch_stream_copy(src_dev, dst_dev, bytes, blocks_per_cu, static_cast<hipStream_t>(hip_stream)));
+  return LBPF_OK;
+}
+
+int lb_pf_state_ptr(const lbpf_handle *h, int sim, void **state, size_t *bytes) {
+  int rc = check_sim(h, sim);
+  if (rc) return rc;
+  const SimHost &s = h->sims[sim];
+  if (state) *state = h->ws + s.state_off[h->parity];
+  if (bytes) *bytes = s.state_bytes;
   return LBPF_OK;
 }
 

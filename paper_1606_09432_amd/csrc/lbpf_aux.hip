@@ -1,4 +1,5 @@
 // Initial state, field import/export and FP64 diagnostics reductions.
+#include <algorithm>
 #include <cmath>
 
 #include "lbpf_kernels.hpp"
@@ -30,7 +31,12 @@ __device__ double init_phi(const SimDev &sd, const InitSrc &src, int x, int yp, 
   for (int k = 0; k < src.n_seeds; ++k) {
     const SeedDev &s = src.seeds[k];
     const double dx = X - s.x, dy = Y - s.y, dz = Z - s.z;
-    const double d = sqrt((dx * dx + dy * dy) + dz * dz);
+    const double d2 = (dx * dx + dy * dy) + dz * dz;
+    // beyond 20 widths outside the seed tanh is -1 to the last bit (1 - |tanh|
+    // < 1e-17), which cannot raise the maximum: skipping it changes nothing
+    const double reach = s.r + 20.0 * sd.width;
+    if (reach > 0.0 && d2 > reach * reach) continue;
+    const double d = sqrt(d2);
     const double v = tanh((s.r - d) / sd.width);  // Eq. Initial_Condition, lattice units
     if (v > ph) ph = v;
   }
@@ -124,7 +130,7 @@ __global__ __launch_bounds__(256) void init_kernel(SimDev sd, int16_t *ids_out, 
     for (int i = LP::Q - 1; i >= 0; --i) {
       const double eN = (LP::E[i][0] * Nv[0] + LP::E[i][1] * Nv[1]) + LP::E[i][2] * Nv[2];
       const double geq = LP::W[i] * (ph - sd.kphi * eN);
-      typename ST::T v = typename ST::T(ST::OFF ? -LP::W[i] * sd.kphi * eN : geq);
+      typename ST::T v = typename ST::T(ST::OFF ? -LP::W[i] * sd.kphi * eN * ST::SC : geq);
       if constexpr (ST::COMP) {
         if (i == 0)
           v = -rsum;
@@ -147,7 +153,7 @@ __global__ __launch_bounds__(256) void init_kernel(SimDev sd, int16_t *ids_out, 
       } else if (in_range(tx, sd.nx) && (DIM == 2 || in_range(ty, sd.nyp)) && in_range(tm, sd.nm)) {
         ut = init_u<DIM>(sd, src, tx, ty, tm);
       }
-      const double v = ST::OFF ? LU::W[i] * (ut - uy) : LU::W[i] * ut;
+      const double v = ST::OFF ? LU::W[i] * (ut - uy) * ST::SC : LU::W[i] * ut;
       ST::st(F + (long long)i * sd.fstride + idx, typename ST::T(v));
     }
   }
@@ -317,7 +323,7 @@ __global__ __launch_bounds__(256) void export_kernel(SimDev sd, double *phi, dou
     if (ids) ids[c] = sd.use_ids ? sd.id_in[idx] : int16_t(0);
     if (g) {
       for (int i = 0; i < LP::Q; ++i) {
-        const double h = (double)ST::ld(G + (long long)i * sd.fstride + idx);
+        const double h = (double)ST::ld(G + (long long)i * sd.fstride + idx) / ST::SC;
         g[(long long)i * total + c] = ST::OFF ? LP::W[i] * ph + h : h;
       }
     }
@@ -370,6 +376,45 @@ __global__ void state_header_kernel(StateHeader *dst, StateHeader h) {
 
 hipError_t launch_state_header(StateHeader *dst, const StateHeader &h, hipStream_t st) {
   hipLaunchKernelGGL(state_header_kernel, dim3(1), dim3(64), 0, st, dst, h);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Streaming copy: each thread moves four 16-byte vectors per round (loads
+// first, then stores), consecutive threads consecutive vectors; a grid of a
+// few work-groups per CU strides over the array.  A tail shorter than 16 bytes
+// is copied byte by byte by the first threads.
+// ---------------------------------------------------------------------------
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void stream_copy_kernel(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
+                                                          size_t n16, const unsigned char *__restrict__ tsrc,
+                                                          unsigned char *__restrict__ tdst, int ntail) {
+  constexpr int U = 4;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (; i + (U - 1) * stride < n16; i += U * stride) {
+    u32x4 v[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) v[k] = __builtin_nontemporal_load(src + i + k * stride);
+#pragma unroll
+    for (int k = 0; k < U; ++k) __builtin_nontemporal_store(v[k], dst + i + k * stride);
+  }
+  for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+  if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tdst[threadIdx.x] = tsrc[threadIdx.x];
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, size_t bytes, int blocks_per_cu, hipStream_t st) {
+  int dev = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return e;
+  const size_t n16 = bytes / 16;
+  const int ntail = (int)(bytes % 16);
+  const int grid = std::max(1, ncu * std::max(1, blocks_per_cu));
+  hipLaunchKernelGGL(stream_copy_kernel, dim3(grid), dim3(256), 0, st, static_cast<const u32x4 *>(src),
+                     static_cast<u32x4 *>(dst), n16, static_cast<const unsigned char *>(src) + n16 * 16,
+                     static_cast<unsigned char *>(dst) + n16 * 16, ntail);
   return hipGetLastError();
 }
 

@@ -141,12 +141,18 @@ template <class E> __device__ __forceinline__ void nt_store(E *p, E v) {
 // ---------------------------------------------------------------------------
 // Storage: FP64 distributions, or FP32 arithmetic on offsets stored in FP32/FP16.
 // ---------------------------------------------------------------------------
+// SC: stored units per true unit of an offset.  FP16 offsets are stored
+// multiplied by 2^12, so that the small offsets of the bulk (down to about
+// 1.5e-8) stay above the FP16 subnormal range; |offsets| stay far below
+// 65504 / 2^12 = 16.  A power of two scales without rounding.  The step folds
+// SC into its compile-time weights, so the scale costs no instruction.
 struct StF64 {
   using T = double;  // arithmetic
   using S = double;  // stored distribution
   using P = double;  // stored phi
   static constexpr bool OFF = false;
   static constexpr bool COMP = false;
+  static constexpr double SC = 1.0;
   static __device__ __forceinline__ T ld(const S *p) { return *p; }
   static __device__ __forceinline__ void st(S *p, T v) { nt_store(p, S(v)); }
   static __device__ __forceinline__ S enc(T v) { return v; }
@@ -158,6 +164,7 @@ struct StF32 {
   using P = float;
   static constexpr bool OFF = true;
   static constexpr bool COMP = false;
+  static constexpr double SC = 1.0;
   static __device__ __forceinline__ T ld(const S *p) { return *p; }
   static __device__ __forceinline__ void st(S *p, T v) { nt_store(p, S(v)); }
   static __device__ __forceinline__ S enc(T v) { return v; }
@@ -170,6 +177,7 @@ struct StF16 {
   static constexpr bool OFF = true;
   // the rest offset balances the rounded others (FP16 rounding is coarse)
   static constexpr bool COMP = true;
+  static constexpr double SC = 4096.0;
   static __device__ __forceinline__ T ld(const S *p) { return __half2float(*p); }
   static __device__ __forceinline__ void st(S *p, T v) { nt_store(p, __float2half_rn(v)); }
   static __device__ __forceinline__ S enc(T v) { return __float2half_rn(v); }
@@ -179,13 +187,29 @@ struct StF16 {
 // Anisotropy entry as the kernels see it (cos/sin of q phi0 precomputed on the
 // host).  rot = 1: the polynomial is evaluated at R n (R row-major), a crystal
 // orientation of Sec. 4.3 in 3D; rot = 0 skips the rotation (identity).
+// The three cubic kinds share one polynomial, a = c0 + c1 Q + c2 S with
+// Q = n_x^4 + n_y^4 + n_z^4 and S = n_x^2 n_y^2 n_z^2:
+//   Eq. As_Function_Classical  c0 = 1 - 3 eps, c1 = 4 eps, c2 = 0;
+//   Eq. As_MatSci              c0 = 1 - 3 eps/5 - 17 gamma/7, c1 = eps + 3 gamma, c2 = 66 gamma;
+//   Eq. As_Function_S          c0 = 1, c1 = 0, c2 = 66 gamma (read with the constant 1).
+// Every coefficient is kept in FP64 and in FP32 (the FP32-arithmetic forms
+// read the latter and convert nothing).
 struct AnisoDev {
   int kind;
   int q;
   double eps, gamma, cr, ci;
   int rot;
   double R[9];
+  double c0, c1, c2;
+  float epsf, crf, cif, c0f, c1f, c2f;
+  float Rf[9];
 };
+template <class T> __host__ __device__ __forceinline__ T pick(double d, float f) {
+  if constexpr (sizeof(T) == sizeof(float))
+    return f;
+  else
+    return d;
+}
 constexpr int kMaxAniso = 256;
 
 enum { K_ISO = 0, K_SECTORAL = 1, K_CUBIC = 2, K_CUBIC_HAK = 3, K_CUBIC_S = 4 };
@@ -201,6 +225,7 @@ struct SimDev {
   double lambda;   // coupling
   double omega_u;  // 1 / eta_u
   double xi2;      // xi^2 (index threshold on |p|^2)
+  float kphi_f, s_f, lambda_f, omega_u_f, xi2_f;  // the same in FP32
   double width;    // sqrt(2) W0 / dx (seed profile width, lattice units)
   double u0;       // -delta
   const void *g_in;
@@ -259,7 +284,7 @@ __host__ __device__ __forceinline__ void aniso_eval(const AnisoDev &A, T nx, T n
       pr = tr;
       pi = ti;
     }
-    const T cr = T(A.cr), ci = T(A.ci), eps = T(A.eps);
+    const T cr = pick<T>(A.cr, A.crf), ci = pick<T>(A.ci, A.cif), eps = pick<T>(A.eps, A.epsf);
     const T zr = pr * nx - pi * ny, zi = pr * ny + pi * nx;
     a = T(1) + eps * (zr * cr - zi * ci);
     const T qf = T(A.q);
@@ -267,37 +292,20 @@ __host__ __device__ __forceinline__ void aniso_eval(const AnisoDev &A, T nx, T n
     Gy = -(eps * (qf * (pr * ci + pi * cr)));
     return;
   }
+  if (A.kind == K_ISO) {
+    a = T(1);
+    return;
+  }
+  // cubic kinds: c0 + c1 Q + c2 S, grad Q = 4 (n_x^3, ..), grad S = 2 n_x n_y^2 n_z^2, ..
+  const T c0 = pick<T>(A.c0, A.c0f), c1 = pick<T>(A.c1, A.c1f), c2 = pick<T>(A.c2, A.c2f);
   const T x2 = nx * nx, y2 = ny * ny, z2 = nz * nz;
   const T Q = (x2 * x2 + y2 * y2) + z2 * z2;
-  const T eps = T(A.eps);
-  if (A.kind == K_CUBIC) {
-    a = (T(1) - T(3) * eps) + T(4) * eps * Q;
-    Gx = T(16) * eps * (x2 * nx);
-    Gy = T(16) * eps * (y2 * ny);
-    Gz = T(16) * eps * (z2 * nz);
-    return;
-  }
-  if (A.kind == K_CUBIC_HAK) {
-    const T gam = T(A.gamma);
-    const T S = (x2 * y2) * z2;
-    a = T(1) + eps * (Q - T(3.0 / 5.0)) + gam * ((T(3) * Q + T(66) * S) - T(17.0 / 7.0));
-    const T dQx = T(4) * (x2 * nx), dQy = T(4) * (y2 * ny), dQz = T(4) * (z2 * nz);
-    const T dSx = T(2) * nx * (y2 * z2), dSy = T(2) * ny * (x2 * z2), dSz = T(2) * nz * (x2 * y2);
-    Gx = eps * dQx + gam * (T(3) * dQx + T(66) * dSx);
-    Gy = eps * dQy + gam * (T(3) * dQy + T(66) * dSy);
-    Gz = eps * dQz + gam * (T(3) * dQz + T(66) * dSz);
-    return;
-  }
-  if (A.kind == K_CUBIC_S) {
-    // Eq. As_Function_S with the constant 1 (1 + 66 gamma S)
-    const T g66 = T(66) * T(A.gamma);
-    a = T(1) + g66 * ((x2 * y2) * z2);
-    Gx = g66 * (T(2) * nx * (y2 * z2));
-    Gy = g66 * (T(2) * ny * (x2 * z2));
-    Gz = g66 * (T(2) * nz * (x2 * y2));
-    return;
-  }
-  a = T(1);
+  const T yz = y2 * z2, xz = x2 * z2, xy = x2 * y2;
+  a = c0 + c1 * Q + c2 * (xy * z2);
+  const T f1 = T(4) * c1, f2 = T(2) * c2;
+  Gx = nx * (f1 * x2 + f2 * yz);
+  Gy = ny * (f1 * y2 + f2 * xz);
+  Gz = nz * (f1 * z2 + f2 * xy);
 }
 
 // An entry at direction n: the polynomial at m = R n, and by the chain rule
@@ -309,14 +317,16 @@ __host__ __device__ __forceinline__ void aniso_eval_rot(const AnisoDev &A, T nx,
     aniso_eval<T>(A, nx, ny, nz, a, Gx, Gy, Gz);
     return;
   }
-  const T mx = (T(A.R[0]) * nx + T(A.R[1]) * ny) + T(A.R[2]) * nz;
-  const T my = (T(A.R[3]) * nx + T(A.R[4]) * ny) + T(A.R[5]) * nz;
-  const T mz = (T(A.R[6]) * nx + T(A.R[7]) * ny) + T(A.R[8]) * nz;
+  T R[9];
+  for (int k = 0; k < 9; ++k) R[k] = pick<T>(A.R[k], A.Rf[k]);
+  const T mx = (R[0] * nx + R[1] * ny) + R[2] * nz;
+  const T my = (R[3] * nx + R[4] * ny) + R[5] * nz;
+  const T mz = (R[6] * nx + R[7] * ny) + R[8] * nz;
   T Hx, Hy, Hz;
   aniso_eval<T>(A, mx, my, mz, a, Hx, Hy, Hz);
-  Gx = (T(A.R[0]) * Hx + T(A.R[3]) * Hy) + T(A.R[6]) * Hz;
-  Gy = (T(A.R[1]) * Hx + T(A.R[4]) * Hy) + T(A.R[7]) * Hz;
-  Gz = (T(A.R[2]) * Hx + T(A.R[5]) * Hy) + T(A.R[8]) * Hz;
+  Gx = (R[0] * Hx + R[3] * Hy) + R[6] * Hz;
+  Gy = (R[1] * Hx + R[4] * Hy) + R[7] * Hz;
+  Gz = (R[2] * Hx + R[5] * Hy) + R[8] * Hz;
 }
 
 // a_s and N = -|p| a (G - n (n.G)) for the gradient p, n = -p/|p|
@@ -352,7 +362,8 @@ __device__ __forceinline__ void flux(const AnisoDev *A, T px, T py, T pz, T &a, 
 // one nonzero component.
 // gather_u returns u^n(y) = sum_i f_i^n(y) and the decoded populations:
 //   FP64:     fd[i] = f_i^n(y)
-//   offsets:  fd[i] = f_i^n(y) - w_i u*(y), stored f*_i = w_i u* + k_i.
+//   offsets:  fd[i] = f_i^n(y) - w_i u*(y), stored f*_i = w_i u* + k_i
+//             (k_i decoded from its stored units).
 // ---------------------------------------------------------------------------
 template <int DIM, class ST>
 __device__ __forceinline__ typename ST::T gather_u(const SimDev &sd, int x, int yp, int m,
@@ -388,7 +399,7 @@ __device__ __forceinline__ typename ST::T gather_u(const SimDev &sd, int x, int 
       else
         src = self;
     }
-    const T kv = ST::ld(F + (long long)d * sd.fstride + src);
+    const T kv = ST::ld(F + (long long)d * sd.fstride + src) * T(1.0 / ST::SC);
     if constexpr (ST::OFF) {
       fd[i] = T(LU::W[i]) * (sd.us_in[src] - us_self) + kv;
     } else {

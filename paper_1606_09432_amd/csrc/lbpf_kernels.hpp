@@ -57,6 +57,9 @@ constexpr size_t kStateHeaderBytes = 256;
 
 // Writes h to device memory dst (stream-ordered; h travels as a kernel argument).
 hipError_t launch_state_header(StateHeader *dst, const StateHeader &h, hipStream_t st);
+// Reads and writes every byte of src once (16-byte vectors, nontemporal):
+// the plain streaming copy that bounds a step moving the same bytes.
+hipError_t launch_stream_copy(const void *src, void *dst, size_t bytes, int blocks_per_cu, hipStream_t st);
 
 // lattice: pair code (0 D2Q9/D2Q5, 1 D3Q19/D3Q7, 2 D3Q15/D3Q7).
 hipError_t launch_step(int lattice, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st);

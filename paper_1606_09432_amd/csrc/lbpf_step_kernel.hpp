@@ -131,6 +131,10 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
   constexpr int NRU = GR + 3;                      // u* and index ring planes
   constexpr int QP = LP::Q, QU = LU::Q;
   constexpr bool OFF = ST::OFF;
+  // offsets (h, k, and the pulled d and gathered fd of the offset forms) are
+  // kept in stored units: SC per true unit; true-unit terms entering them are
+  // scaled through the weights (compile-time constants)
+  constexpr double SC = ST::SC;
   static_assert(NHALO <= NT, "one halo coefficient node per thread at most");
 
   __shared__ T phiS[NRP][PLANE_F];
@@ -424,7 +428,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       if constexpr (IDS) {
         idn = idS[rs4(pm)][pc];
         const T r2 = (p0 * p0 + p1 * p1) + p2 * p2;
-        if (idn == 0 && r2 > T(sd.xi2)) {
+        if (idn == 0 && r2 > pick<T>(sd.xi2, sd.xi2_f)) {
           T best = T(-1e30);
           int16_t bid = 0;
   #pragma unroll
@@ -459,22 +463,23 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
             if (mir & 4) om = -om;
           }
           const float usrc = usS[rs4(pm + om)][pc + oy * PX + ox];
-          fd[i] = T(LU::W[i]) * (usrc - us_self) + kvv;
+          fd[i] = T(LU::W[i] * SC) * (usrc - us_self) + kvv;
         } else {
           fd[i] = kvv;
         }
         usum += fd[i];
       }
-      const T un = OFF ? us_self + usum : usum;
+      const T un = OFF ? us_self + usum * T(1.0 / SC) : usum;
       // a_s, N, relaxation and source
       const AnisoDev *A = IDS ? (idn > 0 ? sd.aniso + idn : nullptr) : sd.aniso;
       T a, Nx, Ny, Nz;
       flux<T>(A, p0, p1, p2, a, Nx, Ny, Nz);
       const T a2 = a * a;
-      const T om_ = rcp(a2 * T(sd.kphi) + T(0.5));
+      const T kph = pick<T>(sd.kphi, sd.kphi_f);
+      const T om_ = rcp(a2 * kph + T(0.5));
       const T o1 = T(1) - phc * phc;
-      const T Qs = (phc - T(sd.lambda) * un * o1) * o1 * T(sd.s);
-      const T cC = -om_ * T(sd.kphi);
+      const T Qs = (phc - pick<T>(sd.lambda, sd.lambda_f) * un * o1) * o1 * pick<T>(sd.s, sd.s_f);
+      const T cC = -om_ * kph;
       const int node = hy * HX + hx;
       parS[ps][0][node] = T(1) - om_;
       parS[ps][1][node] = OFF ? Qs : om_ * phc + Qs;
@@ -596,11 +601,11 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
           const T Acoef = parS[ps][0][node];
           const T Bcoef = parS[ps][1][node];
           const T ia2 = parS[ps][NP - 1][node];
-          const T src = T(LP::W[i]) * (Bcoef + eC(i, ps, node));
+          const T src = T(LP::W[i] * SC) * (Bcoef + eC(i, ps, node));
           if constexpr (OFF) {
             const T phx = phiS[rs(m - cm)][pco - cy * PX - cx];
             const T hs = Acoef * gx_ + src;
-            d[i] = gy_ + ia2 * (T(LP::W[i]) * (phx - phy) + hs - gy_);
+            d[i] = gy_ + ia2 * (T(LP::W[i] * SC) * (phx - phy) + hs - gy_);
           } else {
             const T gs = Acoef * gx_ + src;
             d[i] = gy_ + ia2 * (gs - gy_);
@@ -634,7 +639,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
   #pragma unroll
         for (int i = 0; i < QP; ++i) {
           const int j = LP::OPP[i];
-          const T loc = parS[sc][0][nodeo] * ST::ld(&gy_r[j]) + T(LP::W[j]) * (parS[sc][1][nodeo] + eC(j, sc, nodeo));
+          const T loc = parS[sc][0][nodeo] * ST::ld(&gy_r[j]) + T(LP::W[j] * SC) * (parS[sc][1][nodeo] + eC(j, sc, nodeo));
           dn[i] = unk[i] ? (unk[j] ? loc : d[j]) : d[i];
         }
   #pragma unroll
@@ -643,7 +648,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       T sum = T(0);
   #pragma unroll
       for (int i = 0; i < QP; ++i) sum += d[i];
-      const T phn = OFF ? phy + sum : sum;
+      const T phn = OFF ? phy + sum * T(1.0 / SC) : sum;
       if constexpr (OFF) {
         // the offsets of a node sum to zero. With COMP the rest offset is stored
         // as minus the sum of the others as rounded, so their rounding errors
@@ -667,19 +672,19 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
 
       // heat equation at y: BGK toward w_i u^n with source (phi^{n+1} - phi^n)/2
       const T half_dphi = T(0.5) * (phn - phy);
-      const T om_u = T(sd.omega_u);
+      const T om_u = pick<T>(sd.omega_u, sd.omega_u_f);
       if constexpr (OFF) {
-        const T Sm = u_cur - us_cur;  // sum of the decoded offsets
+        const T Sm = u_cur - us_cur;  // sum of the decoded offsets, true units
         const T keep = T(1) - om_u;
         T rsum = T(0);  // as for g: the rest population balances the rounded others
   #pragma unroll
         for (int i = 1; i < QU; ++i) {
-          const S q = ST::enc(keep * (fd_cur[i] - T(LU::W[i]) * Sm));
+          const S q = ST::enc(keep * (fd_cur[i] - T(LU::W[i] * SC) * Sm));
           nt_store(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(i)) + iyb), q);
           rsum += ST::dec(q);
         }
         ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(0)) + iyb),
-               ST::COMP ? -rsum : keep * (fd_cur[0] - T(LU::W[0]) * Sm));
+               ST::COMP ? -rsum : keep * (fd_cur[0] - T(LU::W[0] * SC) * Sm));
         stb(sd.us_out, iy * 4u, float(u_cur + half_dphi));
       } else {
   #pragma unroll

@@ -208,6 +208,28 @@ def c3(storage: str = "fp16", variant: str = "100", n: int = 512, radius: float 
 C3_STEPS = 20000
 
 
+def dense_3d(storage: str = "fp16", n: int = 512, spacing: int = 64, radius: float = 20.0,
+             lattice: str = "D3Q19_D3Q7", rng_seed: int = 160605) -> SimConfig:
+    """The 512^3 workload's physics (Eq. As_MatSci <100>, Delta = 0.6) with a
+    crystal every `spacing` nodes (centres jittered by up to spacing/8): every
+    node lies within a few interface widths of a crystal, so nearly all take
+    the anisotropic path of the step, as in a late stage of a growth run."""
+    rng = np.random.default_rng(rng_seed)
+    (e1, e2), _ = C3_VARIANTS["100"]
+    k = n // spacing
+    seeds = []
+    for iz in range(k):
+        for iy in range(k):
+            for ix in range(k):
+                j = rng.uniform(-spacing / 8, spacing / 8, size=3)
+                c = (np.array([ix, iy, iz]) + 0.5) * spacing + j
+                seeds.append(Seed(float(c[0]), float(c[1]), float(c[2]), radius, 1))
+    return SimConfig(
+        lattice=lattice, nx=n, ny=n, nz=n, boundary="zero_flux", gradient="dd",
+        storage=storage, delta=0.6, kappa=KAPPA_C0, aniso=[Aniso("cubic_hak", eps=e1, gamma=e2)],
+        seeds=seeds, tip_dir=(1, 0, 0))
+
+
 def c4(count: int = 256, rng_seed: int = 160604, storage: str = "fp32",
        side_lo: int = 2, side_hi: int = 16) -> List[SimConfig]:
     """Ensemble of independent 2D simulations with seeded uneven sizes/parameters."""
