@@ -384,6 +384,65 @@ def run_orientation_spread(storage: str, n_orient: int = 10, side: int = 400, st
     return out
 
 
+def run_c1(steps: int, every: int):
+    """The twenty-crystal 2048^2 workload as stated: each crystal has its own
+    four-fold orientation theta0_k in the index field (Sec. 4.3), run with
+    directional derivatives and with central differences, in FP64 and in FP32
+    offset storage.  Every `every` steps: the mean tip radius R_k of each
+    crystal along theta0_k + m pi/2 (m = 0..3), the coefficient of variation
+    of R_k across the crystals that touch no other yet (Sec. 4.2: an isotropic
+    discretisation grows every orientation alike), and the FP32-vs-FP64
+    differences.  One JSON line per report."""
+    import numpy as np
+    import torch
+
+    import paper_1606_09432_amd as lb
+    from paper_1606_09432_amd import workloads as W
+
+    grads = ("dd", "cd")
+    sims = {st: lb.Simulation([W.c1(st, g) for g in grads]) for st in ("fp64", "fp32")}
+    cfg = W.c1("fp64", "dd")
+    centres = np.array([(s.x, s.y) for s in cfg.seeds])
+    theta = np.array([cfg.aniso[s.id].phi0 for s in cfg.seeds])
+    width = math.sqrt(2.0) * cfg.W0 / cfg.dx
+    dist = np.linalg.norm(centres[:, None, :] - centres[None, :, :], axis=-1) + np.eye(len(centres)) * 1e9
+    done = 0
+    while True:
+        row = {"workload": "C1 2048^2, 20 crystals", "step": done}
+        phis = {}
+        for st, sim in sims.items():
+            for k, g in enumerate(grads):
+                phis[(st, g)] = sim.fields(k)[0].cpu().numpy()
+        torch.cuda.synchronize()
+        for (st, g), phi in phis.items():
+            ny_, nx_ = phi.shape
+            edge = lambda c: min(c[0], c[1], nx_ - 1 - c[0], ny_ - 1 - c[1]) - 3.0  # cubic stencil stays inside
+            rays = np.array([[tip_radius(phi, c[0], c[1], t + m * math.pi / 2,
+                                         rmax=min(200.0, dist[j].min(), edge(c)))
+                              for m in range(4)] for j, (c, t) in enumerate(zip(centres, theta))])
+            R = np.nanmean(rays, axis=1)
+            Rmax = np.nanmax(rays, axis=1)
+            free = np.array([np.all(Rmax[j] + Rmax + 4 * width < dist[j]) for j in range(len(R))])
+            key = f"{st}_{g}"
+            row[key] = {"mean_R": float(np.nanmean(R)), "free_crystals": int(free.sum()),
+                        "cv_free": float(np.nanstd(R[free]) / np.nanmean(R[free])) if free.sum() > 1 else None,
+                        "cv_all": float(np.nanstd(R) / np.nanmean(R))}
+            phis[(st, g) + ("R",)] = R
+        for g in grads:
+            row[f"fp32_vs_fp64_{g}"] = {
+                "max_dphi": float(np.abs(phis[("fp32", g)] - phis[("fp64", g)]).max()),
+                "max_dR": float(np.nanmax(np.abs(phis[("fp32", g, "R")] - phis[("fp64", g, "R")])))}
+        print(json.dumps(row), flush=True)
+        if done >= steps:
+            break
+        k = min(every, steps - done)
+        for sim in sims.values():
+            sim.step(k)
+        done += k
+    for sim in sims.values():
+        sim.close()
+
+
 def run_isotropy(steps: int, storage: str, with_up2: bool = True):
     """The isotropy comparison of Sec. 4.2 (six-fold a_s, 800^2): the DD and CD
     runs advance together as one batched ensemble; prints Err_l2 of each and
@@ -693,6 +752,8 @@ def main():
                     help="only time the paper's 351^3 D3Q15 runs (context for its wall-clock times)")
     ap.add_argument("--orientation", action="store_true",
                     help="only run the DD/CD orientation-dependence measurement (four-fold crystals)")
+    ap.add_argument("--c1", type=int, default=0, metavar="STEPS",
+                    help="only run the twenty-crystal 2048^2 workload (DD/CD x FP64/FP32) for STEPS steps")
     ap.add_argument("--isotropy", type=int, default=0, metavar="STEPS",
                     help="only run the six-fold DD/CD isotropy comparison for STEPS steps")
     ap.add_argument("--acc-steps", type=int, default=2000)
@@ -758,6 +819,9 @@ def main():
         return
     if args.orientation:
         print(json.dumps(run_orientation_spread(args.only or "fp64")), flush=True)
+        return
+    if args.c1:
+        run_c1(args.c1, args.acc_every)
         return
     if args.isotropy:
         print(json.dumps(run_isotropy(args.isotropy, args.only or "fp64")), flush=True)

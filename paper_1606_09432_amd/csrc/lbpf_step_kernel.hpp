@@ -449,13 +449,22 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       T us_self = T(0);
       if constexpr (OFF) us_self = usS[rs4(pm)][pc];
       T usum = T(0);
+      // the node's heat sources all lie inside the box (and beyond no plane):
+      // each sits at the ring offset -e_i, a constant
+      const bool inner = xy_in2 && pm >= 1 && pm + 1 < sd.nm;
   #pragma unroll
       for (int i = 0; i < QU; ++i) {
         const T kvv = T(kv[i]);
         if constexpr (OFF) {
           unsigned src;
           int d, ox, oy, om;
-          heat_src(gx, gy, gm, i, src, d, ox, oy, om);
+          if (inner) {
+            ox = -ex<LU, DIM>(i);
+            oy = -ey<LU, DIM>(i);
+            om = -em<LU, DIM>(i);
+          } else {
+            heat_src(gx, gy, gm, i, src, d, ox, oy, om);
+          }
           if constexpr (MIR) {
             // a ghost node: its mirror node's source, seen from the ghost
             if (mir & 1) ox = -ox;
@@ -481,12 +490,26 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       const T Qs = (phc - pick<T>(sd.lambda, sd.lambda_f) * un * o1) * o1 * pick<T>(sd.s, sd.s_f);
       const T cC = -om_ * kph;
       const int node = hy * HX + hx;
-      parS[ps][0][node] = T(1) - om_;
-      parS[ps][1][node] = OFF ? Qs : om_ * phc + Qs;
-      parS[ps][2][node] = cC * Nx;
-      parS[ps][3][node] = cC * Ny;  // in 2D the lattice y is the march axis
-      if constexpr (DIM == 3) parS[ps][4][node] = cC * Nz;
-      parS[ps][NP - 1][node] = rcp(a2);
+      const T ia2 = rcp(a2);
+      if constexpr (OFF) {
+        // what a pull from this node needs, with 1/a^2 folded in:
+        //   M = 1 - 1/a^2, A' = (1 - w)/a^2, Kc = SC cC N / a^2, K0 = SC (phi + Q s)/a^2
+        const T kc = T(SC) * ia2 * cC;
+        parS[ps][0][node] = T(1) - ia2;
+        parS[ps][1][node] = ia2 * (T(1) - om_);
+        parS[ps][2][node] = kc * Nx;
+        parS[ps][3][node] = kc * Ny;  // in 2D the lattice y is the march axis
+        if constexpr (DIM == 3) parS[ps][4][node] = kc * Nz;
+        parS[ps][NP - 1][node] = (T(SC) * ia2) * (phc + Qs);
+      } else {
+        // FP64: A = 1 - w, B = w phi + Q s, C = cC N and 1/a^2
+        parS[ps][0][node] = T(1) - om_;
+        parS[ps][1][node] = om_ * phc + Qs;
+        parS[ps][2][node] = cC * Nx;
+        parS[ps][3][node] = cC * Ny;
+        if constexpr (DIM == 3) parS[ps][4][node] = cC * Nz;
+        parS[ps][NP - 1][node] = ia2;
+      }
       if (own_node) {
   #pragma unroll
         for (int i = 0; i < QU; ++i) fd_nxt[i] = fd[i];
@@ -496,7 +519,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       }
     };
 
-    // component of C along direction i of the phi lattice
+    // component of Kc (offsets) or C (FP64) along direction i of the phi lattice
     auto eC = [&](int i, int ps, int node) -> T {
       T v = T(0);
       if (LP::E[i][0] != 0) v += T(LP::E[i][0]) * parS[ps][2][node];
@@ -587,7 +610,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
           }
         });
       };
-      T phy;
+      T phy, scphy;
       T d[QP];
       // the pulls (a source beyond a mirror plane is its ghost coefficient node)
       auto pull = [&]() {
@@ -598,17 +621,16 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
           const int node = nodeo - cy * HX - cx;
           const T gy_ = ST::ld(&gy_r[i]);
           const T gx_ = ST::ld(&gx_r[i]);
-          const T Acoef = parS[ps][0][node];
-          const T Bcoef = parS[ps][1][node];
-          const T ia2 = parS[ps][NP - 1][node];
-          const T src = T(LP::W[i] * SC) * (Bcoef + eC(i, ps, node));
           if constexpr (OFF) {
-            const T phx = phiS[rs(m - cm)][pco - cy * PX - cx];
-            const T hs = Acoef * gx_ + src;
-            d[i] = gy_ + ia2 * (T(LP::W[i] * SC) * (phx - phy) + hs - gy_);
+            // d = h(y) + [h*(x) + w_i (phi(x) - phi(y)) - h(y)]/a^2(x)
+            //   = M h(y) + A' h(x) + w_i (K0 + e_i.Kc - SC phi(y)/a^2(x))
+            const T Mc = parS[ps][0][node];
+            const T Ap = parS[ps][1][node];
+            const T t = scphy * (Mc - T(1)) + (parS[ps][NP - 1][node] + eC(i, ps, node));
+            d[i] = Mc * gy_ + (T(LP::W[i]) * t + Ap * gx_);
           } else {
-            const T gs = Acoef * gx_ + src;
-            d[i] = gy_ + ia2 * (gs - gy_);
+            const T gs = parS[ps][0][node] * gx_ + T(LP::W[i]) * (parS[ps][1][node] + eC(i, ps, node));
+            d[i] = gy_ + parS[ps][NP - 1][node] * (gs - gy_);
           }
         }
       };
@@ -623,6 +645,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
         else
           load_generic(std::true_type{});
         phy = phiS[rs(m)][pco];
+        scphy = T(SC) * phy;
         pull();
       } else {
         if (fast)
@@ -630,16 +653,25 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
         else
           load_generic(std::false_type{});
         phy = phiS[rs(m)][pco];
+        scphy = T(SC) * phy;
         pull();
       }
       if (walls) {
         // bounce-back: an unknown incoming population takes the opposite one; if
         // that is unknown too, the local post-collision opposite population
+        // (offsets: h*_j(y) = a^2 [A' h_j(y) + w_j (K0 + e_j.Kc)] - w_j SC phi(y))
         T dn[QP];
+        const T a2o = OFF ? rcp(T(1) - parS[sc][0][nodeo]) : T(0);
   #pragma unroll
         for (int i = 0; i < QP; ++i) {
           const int j = LP::OPP[i];
-          const T loc = parS[sc][0][nodeo] * ST::ld(&gy_r[j]) + T(LP::W[j] * SC) * (parS[sc][1][nodeo] + eC(j, sc, nodeo));
+          T loc;
+          if constexpr (OFF)
+            loc = a2o * (parS[sc][1][nodeo] * ST::ld(&gy_r[j]) +
+                         T(LP::W[j]) * (parS[sc][NP - 1][nodeo] + eC(j, sc, nodeo))) -
+                  T(LP::W[j]) * scphy;
+          else
+            loc = parS[sc][0][nodeo] * ST::ld(&gy_r[j]) + T(LP::W[j]) * (parS[sc][1][nodeo] + eC(j, sc, nodeo));
           dn[i] = unk[i] ? (unk[j] ? loc : d[j]) : d[i];
         }
   #pragma unroll
