@@ -55,14 +55,17 @@ def traffic_key(lattice: str, storage: str) -> str:
     return storage if lattice == "D3Q19_D3Q7" else f"{lattice.split('_')[0].lower()}_{storage}"
 
 
-def measured_traffic(lattice: str, storage: str):
+BATCHED_KEY = "c4_ensemble_fp32"
+
+
+def measured_traffic(lattice: str, storage: str, key: str = None):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
-    ent = d.get("kernels", {}).get(traffic_key(lattice, storage))
+    ent = d.get("kernels", {}).get(key or traffic_key(lattice, storage))
     if not ent or ent.get("kernel_sha") != kernel_sha():
         return None
     return ent.get("bytes_per_launch")
@@ -81,13 +84,15 @@ def time_stream_copy(sim, reps: int = 5):
     if other is None:
         return None, 0
     stream = torch.cuda.current_stream()
-    lb.stream_copy(src, other, nbytes)
+    # one work-group of 256 threads per compute unit: the fastest of 1..32 per
+    # CU in a sweep on an 8 GiB copy (5.44 TB/s; 4.87 at 8 per CU)
+    lb.stream_copy(src, other, nbytes, 1)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        lb.stream_copy(src, other, nbytes)
+        lb.stream_copy(src, other, nbytes, 1)
     e1.record(stream)
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / reps, 2 * nbytes
@@ -127,7 +132,7 @@ def run_gpu(cfg, steps: int, warmup: int, autotune: bool, copy_ceiling: bool = F
         cms, cbytes = time_stream_copy(sim)
         if cms:
             copy = {"ms": cms, "bytes": cbytes, "GBps": cbytes / (cms * 1e-3) / 1e9,
-                    "kind": "lb_pf_stream_copy of the state block into the other block (16-byte nontemporal "
+                    "kind": "lb_pf_stream_copy of the state block into the other block (one work-group of 256 per CU, 16-byte nontemporal "
                             "vectors), read + written bytes"}
             print(f"[bench] {cfg.storage}: state-block copy {cbytes / 1e9:.2f} GB in {cms:.3f} ms, "
                   f"{copy['GBps']:.0f} GB/s", file=sys.stderr, flush=True)
@@ -210,7 +215,9 @@ def run_batched(steps: int, warmup: int):
             "nodes": nodes, "value": nodes * steps / (ms * 1e-3) / 1e6, "unit": "MLUPS",
             "ms_per_step": ms / steps, "dtype": "f32", "chunk": tile[1],
             "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "bytes_per_node_step": b_alg}}
+                         "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": measured_traffic("D2Q9_D2Q5", "fp32", BATCHED_KEY),
+                         "bytes_per_node_step": b_alg}}
 
 
 def run_accuracy(workload: str, n: int, steps: int, every: int, variant: str):
@@ -409,29 +416,43 @@ def run_c1(steps: int, every: int):
     done = 0
     while True:
         row = {"workload": "C1 2048^2, 20 crystals", "step": done}
+        if done == 0:
+            row["theta0"] = [round(float(t), 4) for t in theta]
+            row["nearest"] = [round(float(d), 1) for d in dist.min(axis=1)]
         phis = {}
         for st, sim in sims.items():
             for k, g in enumerate(grads):
                 phis[(st, g)] = sim.fields(k)[0].cpu().numpy()
         torch.cuda.synchronize()
+        radii = {}
         for (st, g), phi in phis.items():
             ny_, nx_ = phi.shape
-            edge = lambda c: min(c[0], c[1], nx_ - 1 - c[0], ny_ - 1 - c[1]) - 3.0  # cubic stencil stays inside
-            rays = np.array([[tip_radius(phi, c[0], c[1], t + m * math.pi / 2,
-                                         rmax=min(200.0, dist[j].min(), edge(c)))
+            # distance to the box edge, less the reach of the cubic ray stencil
+            edge = np.array([min(c[0], c[1], nx_ - 1 - c[0], ny_ - 1 - c[1]) - 3.0 for c in centres])
+            rmax = np.minimum(np.minimum(200.0, dist.min(axis=1)), edge)
+            rays = np.array([[tip_radius(phi, c[0], c[1], t + m * math.pi / 2, rmax=rmax[j])
                               for m in range(4)] for j, (c, t) in enumerate(zip(centres, theta))])
-            R = np.nanmean(rays, axis=1)
-            Rmax = np.nanmax(rays, axis=1)
-            free = np.array([np.all(Rmax[j] + Rmax + 4 * width < dist[j]) for j in range(len(R))])
+            whole = np.all(np.isfinite(rays), axis=1)
+            R = np.where(whole, np.nanmean(np.where(whole[:, None], rays, 0.0), axis=1), np.nan)
+            # a crystal with a ray beyond its search radius has reached at least that
+            Rmax = np.where(whole, np.max(np.where(whole[:, None], rays, 0.0), axis=1), rmax)
+            # free: all four tips found, and the interfaces (4 widths apart) meet
+            # neither another crystal's nor the box wall
+            free = np.array([whole[j] and Rmax[j] + 2 * width < edge[j] and
+                             np.all((Rmax[j] + Rmax + 4 * width < dist[j]) | (np.arange(len(R)) == j))
+                             for j in range(len(R))])
             key = f"{st}_{g}"
-            row[key] = {"mean_R": float(np.nanmean(R)), "free_crystals": int(free.sum()),
-                        "cv_free": float(np.nanstd(R[free]) / np.nanmean(R[free])) if free.sum() > 1 else None,
-                        "cv_all": float(np.nanstd(R) / np.nanmean(R))}
-            phis[(st, g) + ("R",)] = R
+            row[key] = {"mean_R_free": float(R[free].mean()) if free.any() else None,
+                        "free_crystals": int(free.sum()),
+                        "cv_free": float(R[free].std() / R[free].mean()) if free.sum() > 1 else None,
+                        "R": [None if not np.isfinite(r) else round(float(r), 4) for r in R],
+                        "free": [int(f) for f in free]}
+            radii[(st, g)] = R
         for g in grads:
             row[f"fp32_vs_fp64_{g}"] = {
                 "max_dphi": float(np.abs(phis[("fp32", g)] - phis[("fp64", g)]).max()),
-                "max_dR": float(np.nanmax(np.abs(phis[("fp32", g, "R")] - phis[("fp64", g, "R")])))}
+                "max_dR": float(np.nanmax(np.abs(radii[("fp32", g)] - radii[("fp64", g)])))
+                if np.isfinite(radii[("fp32", g)] - radii[("fp64", g)]).any() else None}
         print(json.dumps(row), flush=True)
         if done >= steps:
             break
@@ -654,19 +675,29 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, 
           f"WRITE_SIZE = {copy_w:.0f}, so bytes = FETCH_SIZE x {ff:.1f} + WRITE_SIZE x {fw:.1f}.", "",
           "| kernel | FETCH_SIZE | WRITE_SIZE | read bytes | written bytes | bytes/launch | bytes/node |",
           "|---|---|---|---|---|---|---|"]
+    from paper_1606_09432_amd import workloads as W
+
+    ens_nodes = sum(c.nodes for c in W.c4())
     for k in sorted(set(fe) | set(wr)):
-        # the 3D workload's kernels: lattice pair 1 (D3Q19) or 2 (D3Q15)
-        lat = {"step_kernel<1,": "D3Q19_D3Q7", "step_kernel<2,": "D3Q15_D3Q7"}.get(k[:14])
+        # the 3D workload's kernels: lattice pair 1 (D3Q19) or 2 (D3Q15); the
+        # batched 2D ensemble's kernel (lattice pair 0, BATCH = true)
+        targs = [a.strip() for a in k[k.find("<") + 1:k.rfind(">")].split(",")] if "<" in k else []
+        lat = {"step_kernel<1,": "D3Q19_D3Q7", "step_kernel<2,": "D3Q15_D3Q7",
+               "step_kernel<0,": "D2Q9_D2Q5"}.get(k[:14])
         st = next((v for kk, v in STORAGE_OF_KERNEL.items() if kk in k), None)
         f, w = fe.get(k, {}).get("FETCH_SIZE"), wr.get(k, {}).get("WRITE_SIZE")
         if lat is None or st is None or f is None or w is None:
             continue
-        st = traffic_key(lat, st)
+        if lat == "D2Q9_D2Q5":
+            if len(targs) < 5 or targs[4] != "true" or st != "fp32":
+                continue
+            st, nodes = BATCHED_KEY, ens_nodes
+        else:
+            st, nodes = traffic_key(lat, st), 512 ** 3
         rb, wb = f * ff, w * fw
-        nodes = 512 ** 3
         res["kernels"][st] = {"kernel": k, "kernel_sha": sha, "fetch_counter": f, "write_counter": w,
                               "read_bytes": rb, "write_bytes": wb, "bytes_per_launch": rb + wb,
-                              "bytes_per_node": (rb + wb) / nodes}
+                              "nodes": nodes, "bytes_per_node": (rb + wb) / nodes}
         md.append(f"| `{k}` | {f:.0f} | {w:.0f} | {rb:.4g} | {wb:.4g} | {rb + wb:.4g} | "
                   f"{(rb + wb) / nodes:.1f} |")
     md += ["", f"Kernel source hash: {sha} (comments and blank lines excluded; bench.py reports this traffic only "

@@ -324,8 +324,8 @@ int set_tile(SimHost &s, int ty, int chunk) {
     if (s.dim == 2 && ty != 1) return fail(LBPF_ERR_UNSUPPORTED, "2D tiles are one row high");
     if (s.dim == 3 && ty != 4 && ty != 8 && ty != 12)
       return fail(LBPF_ERR_UNSUPPORTED, "tile_y must be 4, 8 or 12");
-    if (s.dim == 3 && ty != 4 && s.storage == LBPF_FP64)
-      return fail(LBPF_ERR_UNSUPPORTED, "tile_y above 4 needs FP32 arithmetic");
+    if (s.dim == 3 && ty == 12 && s.storage == LBPF_FP64)
+      return fail(LBPF_ERR_UNSUPPORTED, "tile_y 12 needs FP32 arithmetic");
     if (s.dim == 3 && ty != 4 && s.cfg.gradient == LBPF_GRAD_UP2)
       return fail(LBPF_ERR_UNSUPPORTED, "the upwind gradient runs on 4-row tiles");
     t.ty = ty;
@@ -949,7 +949,8 @@ int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream) {
   float best = 1e30f;
   int bty = s0.tile.ty, bch = h->batch.on ? h->batch.chunk : s0.tile.chunk;
   for (int ty : tys) {
-    if (s0.dim == 3 && ty != 4 && (s0.storage == LBPF_FP64 || s0.cfg.gradient == LBPF_GRAD_UP2)) continue;
+    if (s0.dim == 3 && ((ty == 12 && s0.storage == LBPF_FP64) || (ty != 4 && s0.cfg.gradient == LBPF_GRAD_UP2)))
+      continue;
     for (int ch : chunks) {
       if (lb_pf_set_tile(h, ty, ch)) continue;
       // warm-up of twice the trial: the trial then starts from the same

@@ -828,9 +828,7 @@ static hipError_t launch_step_ty(const SimDev &sd, const TileDev &tc, hipStream_
   } else {
     switch (tc.ty) {
       case 4: return launch_step_t<K, 4, ST, IDS, MIR>(sd, tc, st);
-      case 8:
-        if constexpr (!std::is_same<ST, StF64>::value) return launch_step_t<K, 8, ST, IDS, MIR>(sd, tc, st);
-        return hipErrorInvalidValue;
+      case 8: return launch_step_t<K, 8, ST, IDS, MIR>(sd, tc, st);
       case 12:
         if constexpr (!std::is_same<ST, StF64>::value) return launch_step_t<K, 12, ST, IDS, MIR>(sd, tc, st);
         return hipErrorInvalidValue;

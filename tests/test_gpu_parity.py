@@ -440,7 +440,7 @@ def test_fp16_offsets_of_a_node_sum_to_zero(gpu, oracle_mod, lattice):
 # ---------------------------------------------------------------------------
 # Launch shape, determinism, checkpoint, batching.
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("storage,tiles", [("fp64", [(4, 8), (4, 64), (4, 5)]),
+@pytest.mark.parametrize("storage,tiles", [("fp64", [(4, 8), (4, 64), (4, 5), (8, 32), (8, 7)]),
                                            ("fp16", [(12, 32), (4, 7), (8, 64), (12, 5), (12, 9)])])
 def test_tile_shapes_bitwise_equal(gpu, storage, tiles):
     cfg = W.small_3d(storage=storage, nx=70, ny=37, nz=29, radius=6)
