@@ -643,6 +643,18 @@ def summarize_trace(d, command, bench_json=None):
         for st, r in b.get("d3q15", {}).items():
             out.append(f"- D3Q15 {st}: {r['ms_per_step']:.4f} ms, {r['value']:.1f} {r['unit']}, "
                        f"{r['roofline']['achieved']:.0f} GB/s algorithmic")
+        for st in ("fp16", "fp64"):
+            r = b.get("dense", {}).get(st)
+            if r:
+                out.append(f"- dense interfaces {st}: {r['ms_per_step']:.4f} ms, {r['value']:.1f} {r['unit']}, "
+                           f"anisotropic fraction {r['anisotropic_fraction']:.3f}")
+        for st, c in [(b["config"]["storage"], b.get("stream_copy"))] + [
+                (st, b[st].get("stream_copy")) for st in ("fp64", "fp32", "fp16") if st in b]:
+            if c:
+                out.append(f"- state-block copy ({st}): {c['ms']:.4f} ms, {c['bytes'] / 1e9:.2f} GB read + written, "
+                           f"{c['GBps']:.0f} GB/s (`lb_pf_stream_copy`)")
+        if b.get("hbm_copy"):
+            out.append(f"- torch copy_: {json.dumps(b['hbm_copy'])}")
     return "\n".join(out) + "\n"
 
 
@@ -822,7 +834,7 @@ def main():
         open(args.out, "w").write(text) if args.out else print(text)
         return
     if args.summarize_sq:
-        run = "python bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-batched"
+        run = "python bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-batched --no-dense"
         cmd = args.command or "\n".join(
             [f"rocprofv3 --pmc {' '.join(p)} -d {d} -o bench -- {run}" for p, d in zip(SQ_PASSES, args.summarize_sq)]
             + [f"python bench.py --summarize-sq {' '.join(args.summarize_sq)}" + (f" --out {args.out}" if args.out else "")])
@@ -831,7 +843,7 @@ def main():
         return
     if args.summarize_traffic:
         fd, wd, cfd, cwd = args.summarize_traffic
-        run = "python bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-batched"
+        run = "python bench.py --steps 3 --warmup 1 --no-cpu-baseline --no-dense"
         cal = f"python bench.py --calibrate-copy {args.copy_mib}"
         cmd = args.command or "\n".join([
             f"rocprofv3 --pmc FETCH_SIZE -d {fd} -o bench -- {run}",
