@@ -618,19 +618,43 @@ def _short(name):
 
 def summarize_trace(d, command, bench_json=None):
     """Per-kernel dispatch statistics (--kernel-trace) as markdown."""
-    rows = {}
+    rows, spans = {}, {}
     for db in _dbs(d):
         con = sqlite3.connect(db)
-        q = ("SELECT S.display_name, K.end - K.start FROM rocpd_kernel_dispatch K "
+        q = ("SELECT S.display_name, K.start, K.end FROM rocpd_kernel_dispatch K "
              "JOIN rocpd_info_kernel_symbol S ON S.id = K.kernel_id AND S.guid = K.guid")
-        for name, dur in con.execute(q):
-            rows.setdefault(_short(name), []).append(dur)
+        for name, t0, t1 in con.execute(q):
+            rows.setdefault(_short(name), []).append(t1 - t0)
+            spans.setdefault(_short(name), []).append((t0, t1))
     out = ["# Kernel trace: " + ", ".join(sorted(k for k in rows if "step_kernel" in k)), "",
            "Command (from the repository root):", "", "```", command, "```", "",
            "| kernel | calls | avg ms | min ms | max ms | total ms |", "|---|---|---|---|---|---|"]
     for k, v in sorted(rows.items(), key=lambda kv: -sum(kv[1])):
         out.append(f"| `{k}` | {len(v)} | {sum(v) / len(v) / 1e6:.4f} | {min(v) / 1e6:.4f} | "
                    f"{max(v) / 1e6:.4f} | {sum(v) / 1e6:.3f} |")
+    # one step kernel serves several runs of bench.py (the headline workload,
+    # the dense-interface leg): dispatches more than 50 ms apart start a new run
+    runs = ["", "Runs of each step kernel (dispatches more than 50 ms apart start a new run; the "
+                "first dispatches of a run are its warm-up):", "",
+            "| kernel | run | calls | avg ms |", "|---|---|---|---|"]
+    for k in sorted(spans):
+        if "step_kernel" not in k:
+            continue
+        sp = sorted(spans[k])
+        cur = [sp[0]]
+        parts = []
+        for a, b in zip(sp, sp[1:]):
+            if b[0] - a[1] > 50e6:
+                parts.append(cur)
+                cur = []
+            cur.append(b)
+        parts.append(cur)
+        if len(parts) > 1:
+            for j, p in enumerate(parts):
+                runs.append(f"| `{k}` | {j + 1} | {len(p)} | "
+                            f"{sum(t1 - t0 for t0, t1 in p) / len(p) / 1e6:.4f} |")
+    if len(runs) > 5:
+        out += runs
     if bench_json:
         b = json.loads(open(bench_json).read().strip().splitlines()[-1])
         out += ["", "bench.py's own HIP-event figures in the same run (ms per step = per launch):", ""]
