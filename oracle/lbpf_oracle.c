@@ -32,7 +32,9 @@
  *   - Bounce-back: after streaming, an unknown incoming g_i (its source lies
  *     outside the box) takes the streamed g_i' of the opposite direction at the
  *     same node.  When the source of g_i' is outside too (edges, corners), g_i
- *     takes the post-collision g_i'* of the same node (no nonlocal term).  The
+ *     takes the post-collision g_i'* of the same node (no nonlocal term);
+ *     parity unpinned for this edge and corner case: nothing outside the two
+ *     implementations fixes it (the paper shows a flat wall only).  The
  *     same rule holds for f.  Ghost phi values for gradients are mirrored about
  *     the wall node: phi(-1) = phi(1).
  *   - Symmetric boxes (mirror_low): Sec. 5 computes one octant of a dendrite

@@ -9,6 +9,11 @@
  * It shares no code, header, table or helper with the GPU library: every
  * lattice table, formula and boundary rule below is written out again here.
  *
+ * Parity unpinned: the bounce-back of a population whose source and whose
+ * opposite's source both lie outside a zero-flux box (edges and corners) has
+ * no check outside the two implementations; every other function is pinned by
+ * the CPU test-suite against closed forms, invariants or the paper's values.
+ *
  * Units: everything is in lattice units (node spacing 1, one step = 1) except
  * the physical parameters W0, tau0, lambda, kappa, delta, dx, dt, which are
  * converted with the relations of Sec. 3 (Eq. ThermalDiffusivity and

@@ -384,3 +384,47 @@ def test_asymmetric_entries_are_refused_in_mirror_boxes(oracle_mod, k):
     with pytest.raises(ValueError) as err:
         oracle_mod.OracleSim(cfg.replace(boundary="mirror_low"))
     assert err.value.code == -6
+
+
+# ---------------------------------------------------------------------------
+# Crystal-index update (Sec. 4.3): a node without a crystal whose gradient
+# exceeds xi takes the index of its phi-lattice neighbour that has one and
+# the largest phi; of two such neighbours with the same phi, the smaller
+# index wins; a node that has an index keeps it.  Hand-built fields, one step.
+# ---------------------------------------------------------------------------
+def _index_case(oracle_mod, cells):
+    n = 12
+    cfg = W.SimConfig(lattice="D2Q9_D2Q5", nx=n, ny=n, nz=1, boundary="periodic", gradient="dd",
+                      storage="fp64", delta=0.5, aniso=[W.Aniso("iso")] + [W.Aniso("iso")] * 3,
+                      seeds=[W.Seed(2.0, 2.0, 0.0, 1.0, 1)], use_ids=True, tip_dir=(1, 0, 0))
+    sim = oracle_mod.OracleSim(cfg)
+    phi = -np.ones((n, n))
+    ids = np.zeros((n, n), dtype=np.int16)
+    for (x, y), (ph, k) in cells.items():
+        phi[y, x] = ph
+        ids[y, x] = k
+    sim.set_fields(phi, np.zeros_like(phi), ids)
+    p = sim.params()["p"]
+    sim.step(1)
+    return sim.ids(), np.sqrt((p ** 2).sum(-1))
+
+
+@pytest.mark.parametrize("east,north,expect", [
+    ((0.5, 2), (0.5, 1), 1),   # equal phi: the smaller index
+    ((0.5, 1), (0.5, 2), 1),   # the same with the neighbours swapped
+    ((0.6, 2), (0.5, 1), 2),   # the larger phi, whatever its index
+    ((0.5, 1), (0.6, 3), 3),
+])
+def test_crystal_index_neighbour_choice(oracle_mod, east, north, expect):
+    ids, pmag = _index_case(oracle_mod, {(7, 6): east, (6, 7): north})
+    assert pmag[6, 6] > 1e-3                    # the centre is in the gradient zone
+    assert ids[6, 6] == expect
+    assert ids[6, 7] == east[1] and ids[7, 6] == north[1]   # indices are kept
+    assert ids[0, 0] == 0                        # far from both: no gradient, no index
+
+
+def test_crystal_index_takes_diagonal_neighbours(oracle_mod):
+    """The candidates are all phi-lattice neighbours, the diagonal ones of D2Q9
+    included: a node whose only indexed neighbour is diagonal takes it."""
+    ids, pmag = _index_case(oracle_mod, {(7, 7): (0.5, 2)})
+    assert pmag[6, 6] > 1e-3 and ids[6, 6] == 2
