@@ -83,8 +83,8 @@ extern "C" {
  * differences.  LBPF_GRAD_UP2 puts the second-order upwind (biased)
  * directional derivatives of Sec. 4.2, [-phi(x+2e) + 4 phi(x+e) - 3 phi(x)]/2,
  * through the same moment (the first-order upwind form through it equals
- * LBPF_GRAD_DD); it is implemented for single simulations on 4-row tiles in
- * 3D, without the index field or mirror planes, with every extent >= 4
+ * LBPF_GRAD_DD); it is implemented for single simulations (not batched
+ * ensembles) without mirror planes, with every extent >= 4
  * (LBPF_ERR_UNSUPPORTED / LBPF_ERR_ARG otherwise). */
 #define LBPF_GRAD_DD 0
 #define LBPF_GRAD_CD 1
@@ -230,8 +230,9 @@ int lb_pf_state_bytes(const lbpf_handle *h, size_t *bytes);
 int lb_pf_save_state(lbpf_handle *h, void *dev_buf, size_t bytes, void *hip_stream);
 int lb_pf_load_state(lbpf_handle *h, const void *dev_buf, size_t bytes, void *hip_stream);
 
-/* Tile shape of the step kernel: tile_y (4, 8 or 12; 8 and 12 need FP32
- * arithmetic) rows of 64 nodes per work-group in 3D (1 in 2D), and `chunk` planes marched per
+/* Tile shape of the step kernel: tile_y (4, 8 or 12; 12 needs FP32
+ * arithmetic; LBPF_GRAD_UP2 takes 4 or 12) rows of 64 nodes per work-group in
+ * 3D (1 in 2D), and `chunk` planes marched per
  * work-group (rows per work item, at least 8, for a batched handle).  0 keeps
  * the current value.  lb_pf_autotune times the candidate shapes on hip_stream
  * (advancing the state by the steps it runs: three times steps_per_trial per

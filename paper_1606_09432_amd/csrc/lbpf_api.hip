@@ -249,8 +249,8 @@ int validate(const lbpf_config &c) {
   if (c.gradient != LBPF_GRAD_DD && c.gradient != LBPF_GRAD_CD && c.gradient != LBPF_GRAD_UP2)
     return fail(LBPF_ERR_ARG, "unknown gradient");
   if (c.gradient == LBPF_GRAD_UP2) {
-    if (c.use_ids || c.boundary == LBPF_MIRROR_LOW)
-      return fail(LBPF_ERR_UNSUPPORTED, "the upwind gradient runs without the index field and mirror planes");
+    if (c.boundary == LBPF_MIRROR_LOW)
+      return fail(LBPF_ERR_UNSUPPORTED, "the upwind gradient runs without mirror planes");
     if (c.nx < 4 || c.ny < 4 || (dim == 3 && c.nz < 4))
       return fail(LBPF_ERR_ARG, "the upwind gradient needs every extent >= 4");
   }
@@ -303,7 +303,7 @@ void units(const lbpf_config &c, SimHost &s) {
 // at least 16 rows each (8 in FP64).
 void default_tile(SimHost &s) {
   TileDev &t = s.tile;
-  t.ty = s.dim == 3 ? ((s.storage == LBPF_FP64 || s.cfg.gradient == LBPF_GRAD_UP2) ? 4 : 12) : 1;
+  t.ty = s.dim == 3 ? (s.storage == LBPF_FP64 ? 4 : 12) : 1;
   t.tiles_x = (s.nx + 63) / 64;
   t.tiles_y = s.dim == 3 ? (s.nyp + t.ty - 1) / t.ty : 1;
   const long long tiles = (long long)t.tiles_x * t.tiles_y;
@@ -326,8 +326,8 @@ int set_tile(SimHost &s, int ty, int chunk) {
       return fail(LBPF_ERR_UNSUPPORTED, "tile_y must be 4, 8 or 12");
     if (s.dim == 3 && ty == 12 && s.storage == LBPF_FP64)
       return fail(LBPF_ERR_UNSUPPORTED, "tile_y 12 needs FP32 arithmetic");
-    if (s.dim == 3 && ty != 4 && s.cfg.gradient == LBPF_GRAD_UP2)
-      return fail(LBPF_ERR_UNSUPPORTED, "the upwind gradient runs on 4-row tiles");
+    if (s.dim == 3 && ty == 8 && s.cfg.gradient == LBPF_GRAD_UP2)
+      return fail(LBPF_ERR_UNSUPPORTED, "the upwind gradient runs on 4- and 12-row tiles");
     t.ty = ty;
   }
   if (chunk > 0) t.chunk = std::min(chunk, s.nm);
@@ -949,7 +949,7 @@ int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream) {
   float best = 1e30f;
   int bty = s0.tile.ty, bch = h->batch.on ? h->batch.chunk : s0.tile.chunk;
   for (int ty : tys) {
-    if (s0.dim == 3 && ((ty == 12 && s0.storage == LBPF_FP64) || (ty != 4 && s0.cfg.gradient == LBPF_GRAD_UP2)))
+    if (s0.dim == 3 && ((ty == 12 && s0.storage == LBPF_FP64) || (ty == 8 && s0.cfg.gradient == LBPF_GRAD_UP2)))
       continue;
     for (int ch : chunks) {
       if (lb_pf_set_tile(h, ty, ch)) continue;

@@ -806,11 +806,23 @@ static hipError_t launch_step_t(const SimDev &sd, const TileDev &tc, hipStream_t
   return hipGetLastError();
 }
 
-// The second-order upwind gradient (GR = 2): one tile height (4 rows in 3D),
-// no index field, no mirror planes, single simulations.
+// The second-order upwind gradient (GR = 2): 4-row tiles in 3D, and 12-row
+// tiles for the FP32-arithmetic forms; with or without the index field; no
+// mirror planes; single simulations.
+template <int K, class ST, bool IDS>
+static hipError_t launch_step_up2_ids(const SimDev &sd, const TileDev &tc, hipStream_t st) {
+  if constexpr (LatOf<K>::DIM == 2) {
+    return launch_step_t<K, 1, ST, IDS, false, 2>(sd, tc, st);
+  } else {
+    if (tc.ty == 4) return launch_step_t<K, 4, ST, IDS, false, 2>(sd, tc, st);
+    if constexpr (!std::is_same<ST, StF64>::value) {
+      if (tc.ty == 12) return launch_step_t<K, 12, ST, IDS, false, 2>(sd, tc, st);
+    }
+    return hipErrorInvalidValue;
+  }
+}
 template <int K, class ST> static hipError_t launch_step_up2_st(const SimDev &sd, const TileDev &tc, hipStream_t st) {
-  if (LatOf<K>::DIM == 3 && tc.ty != 4) return hipErrorInvalidValue;
-  return launch_step_t<K, LatOf<K>::DIM == 3 ? 4 : 1, ST, false, false, 2>(sd, tc, st);
+  return sd.use_ids ? launch_step_up2_ids<K, ST, true>(sd, tc, st) : launch_step_up2_ids<K, ST, false>(sd, tc, st);
 }
 template <int K> static hipError_t launch_step_up2_k(int storage, const SimDev &sd, const TileDev &tc, hipStream_t st) {
   switch (storage) {

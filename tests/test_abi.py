@@ -98,8 +98,9 @@ def test_boundary_values(lib):
 
 
 def test_upwind_gradient_rules(lib):
-    """LBPF_GRAD_UP2 (2) is valid for single simulations without the index
-    field or mirror planes, with every extent >= 4; 3 is no gradient."""
+    """LBPF_GRAD_UP2 (2) is valid for single simulations without mirror planes,
+    with or without the index field, with every extent >= 4; 3 is no
+    gradient."""
     keep = []
     b = C.c_size_t()
 
@@ -113,6 +114,8 @@ def test_upwind_gradient_rules(lib):
     assert rc(base.replace(nx=3)) == -1
     assert rc(base.replace(boundary="mirror_low")) == -6
     assert rc(base, n=2) == -6
+    assert rc(W.c1(n=64, count=3, gradient="up2")) == 0
+    assert rc(W.oriented_3d(gradient="up2")) == 0
     s = lb._to_struct(base, keep)
     s.gradient = 3
     assert lib.lb_pf_workspace_bytes(C.byref(s), 1, C.byref(b)) == -1

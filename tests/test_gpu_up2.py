@@ -98,19 +98,48 @@ def test_up2_offset_storage_accuracy(gpu, oracle_mod, storage, tol):
 
 
 @pytest.mark.parametrize("storage", ["fp64", "fp16"])
-def test_up2_chunks_bitwise_equal(gpu, storage):
+def test_up2_tiles_bitwise_equal(gpu, storage):
     cfg = W.small_3d(nx=70, ny=50, nz=45, storage=storage).replace(gradient="up2")
-    _say(f"up2 chunks {storage}")
+    _say(f"up2 tiles {storage}")
     ref = gpu.Simulation(cfg)
+    assert ref.get_tile()[0] == (4 if storage == "fp64" else 12)
     ref.step(40)
     p0, u0 = _fields(ref)
-    for ch in (5, 16, 45):
+    tiles = [(4, 5), (4, 16), (4, 45)] + ([] if storage == "fp64" else [(12, 7), (12, 45)])
+    for t in tiles:
         s = gpu.Simulation(cfg)
-        s.set_tile(4, ch)
+        s.set_tile(*t)
         s.step(40)
         p, u = _fields(s)
-        assert np.array_equal(p, p0) and np.array_equal(u, u0), ch
-    # tile heights other than 4 are not implemented for this gradient
+        assert np.array_equal(p, p0) and np.array_equal(u, u0), t
+    # 8-row tiles are not built for this gradient, nor 12-row tiles in FP64
     s = gpu.Simulation(cfg)
     with pytest.raises(Exception):
-        s.set_tile(12, 32)
+        s.set_tile(8, 32)
+    if storage == "fp64":
+        with pytest.raises(Exception):
+            s.set_tile(12, 32)
+
+
+# The upwind gradient with the crystal index field (Sec. 4.3): several
+# crystals with their own anisotropy entries, against the oracle.
+@pytest.mark.parametrize("case", ["2d", "3d_d3q19", "3d_d3q15"])
+def test_up2_crystal_index_parity(gpu, oracle_mod, case):
+    if case == "2d":
+        cfg = W.c1(n=96, count=4, gradient="up2")
+        steps = 200
+    else:
+        lat = "D3Q19_D3Q7" if case == "3d_d3q19" else "D3Q15_D3Q7"
+        cfg = W.oriented_3d(gradient="up2", lattice=lat, shape=(44, 40, 36))
+        steps = 40
+    sim, orc = _compare(gpu, oracle_mod, cfg, steps)
+    ids = sim.fields()[2].cpu().numpy()
+    assert np.array_equal(ids, orc.ids())
+    assert len(np.unique(ids)) >= 3
+
+
+# 12-row tiles with the index field in FP16 (the instance that spills a little):
+# within the offset-storage bar of the oracle.
+def test_up2_crystal_index_fp16_12_rows(gpu, oracle_mod):
+    cfg = W.oriented_3d(gradient="up2", storage="fp16", shape=(70, 40, 36))
+    _compare(gpu, oracle_mod, cfg, 40, tol=1e-3, tile=(12, 16))
