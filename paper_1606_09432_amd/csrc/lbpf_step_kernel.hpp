@@ -169,6 +169,13 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       m1 = min(m0 + tc.chunk, sd.nm);
     }
     const int per = sd.periodic;
+    // Without the index field every node takes the one anisotropy entry: read it
+    // here, before the first store of the launch, so that its reads are scalar
+    // and no node waits on a memory read for it.  (Read later from memory, each
+    // read is a vector load followed by a wait for every load in flight,
+    // prefetches included.)
+    AnisoDev a_one{};
+    if constexpr (!IDS) a_one = *sd.aniso;
     // tiles whose pulls (output: 1-node halo) or gathers (coefficients: 2-node
     // halo) stay inside the box without wrapping: plain constant offsets there
     const bool xy_in1 = x0 >= 1 && x0 + TX + 1 <= sd.nx && (DIM == 2 || (y0 >= 1 && y0 + TY + 1 <= sd.nyp));
@@ -480,7 +487,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       }
       const T un = OFF ? us_self + usum * T(1.0 / SC) : usum;
       // a_s, N, relaxation and source
-      const AnisoDev *A = IDS ? (idn > 0 ? sd.aniso + idn : nullptr) : sd.aniso;
+      const AnisoDev *A = IDS ? (idn > 0 ? sd.aniso + idn : nullptr) : &a_one;
       T a, Nx, Ny, Nz;
       flux<T>(A, p0, p1, p2, a, Nx, Ny, Nz);
       const T a2 = a * a;
