@@ -176,6 +176,12 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
     // prefetches included.)
     AnisoDev a_one{};
     if constexpr (!IDS) a_one = *sd.aniso;
+    // mirror planes through node 0 can be reached only by tiles whose rings,
+    // gathers and pulls go below node 3 of an axis (ring halo GR + 1 at most);
+    // every other tile skips the mirror rules (a uniform branch), whose flags
+    // would all be zero there
+    const bool mir_tile =
+        MIR && sd.mirror && (x0 < 4 || (DIM == 3 && y0 < 4) || m0 < 4);
     // tiles whose pulls (output: 1-node halo) or gathers (coefficients: 2-node
     // halo) stay inside the box without wrapping: plain constant offsets there
     const bool xy_in1 = x0 >= 1 && x0 + TX + 1 <= sd.nx && (DIM == 2 || (y0 >= 1 && y0 + TY + 1 <= sd.nyp));
@@ -243,7 +249,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       } else {
         ok = in_range(gx, sd.nx) && (DIM == 2 || in_range(gy, sd.nyp)) && in_range(gm, sd.nm);
         if constexpr (MIR) {
-          if (sd.mirror) {
+          if (mir_tile) {
             ok = gx >= -1 && gx < sd.nx && (DIM == 2 || (gy >= -1 && gy < sd.nyp)) && gm >= -1 && gm < sd.nm;
             mir = (gx == -1 ? 1 : 0) | (DIM == 3 && gy == -1 ? 2 : 0) | (gm == -1 ? 4 : 0);
             gx = abs(gx);
@@ -269,7 +275,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       int sx = gx - cx, sy = gy - cy, sm = gm - cm;
       bool flip = false;
       if constexpr (MIR) {
-        if (sd.mirror) {
+        if (mir_tile) {
           flip = (sx < 0) | (sy < 0) | (sm < 0);
           sx = abs(sx);
           sy = abs(sy);
@@ -318,7 +324,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       off = (unsigned)gy * (unsigned)pitch + (unsigned)gx;
       out = !per && (!in_range(rx, sd.nx) || (DIM == 3 && !in_range(ry, sd.nyp)));
       if constexpr (MIR) {
-        if (sd.mirror) out = rx >= sd.nx || (DIM == 3 && ry >= sd.nyp);  // mirrored below 0
+        if (mir_tile) out = rx >= sd.nx || (DIM == 3 && ry >= sd.nyp);  // mirrored below 0
       }
     };
     if constexpr (!OFF) {
@@ -329,7 +335,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       const int gm = ghost(pm, sd.nm, per);  // pm is always within [-HF, nm + HF - 1]
       bool mout = !per && !in_range(pm, sd.nm);
       if constexpr (MIR) {
-        if (sd.mirror) mout = pm >= sd.nm;  // mirrored below 0
+        if (mir_tile) mout = pm >= sd.nm;  // mirrored below 0
       }
       const unsigned mo = (unsigned)gm * (unsigned)mstride;
   #pragma unroll
@@ -474,9 +480,11 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
           }
           if constexpr (MIR) {
             // a ghost node: its mirror node's source, seen from the ghost
-            if (mir & 1) ox = -ox;
-            if (mir & 2) oy = -oy;
-            if (mir & 4) om = -om;
+            if (mir_tile) {
+              if (mir & 1) ox = -ox;
+              if (mir & 2) oy = -oy;
+              if (mir & 4) om = -om;
+            }
           }
           const float usrc = usS[rs4(pm + om)][pc + oy * PX + ox];
           fd[i] = T(LU::W[i] * SC) * (usrc - us_self) + kvv;
@@ -586,7 +594,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
             // only a component +1 can cross a plane through node 0: the
             // flags of the other components are zero at compile time; a
             // simulation without mirror planes never sets them
-            const bool mir = sd.mirror;
+            const bool mir = mir_tile;
             const bool fx = mir && cx == 1 && gx_o == 0, fy = mir && DIM == 3 && cy == 1 && gy_o == 0,
                        fm = mir && cm == 1 && m == 0;
             fl = (fx ? 1 : 0) | (fy ? 2 : 0) | (fm ? 4 : 0);
