@@ -204,6 +204,9 @@ struct AnisoDev {
   float epsf, crf, cif, c0f, c1f, c2f;
   float Rf[9];
 };
+// An entry read through the constant address space (the step never writes the
+// table).
+using ConstAniso = const __attribute__((address_space(4))) AnisoDev;
 template <class T> __host__ __device__ __forceinline__ T pick(double d, float f) {
   if constexpr (sizeof(T) == sizeof(float))
     return f;
@@ -271,8 +274,8 @@ __device__ __forceinline__ float rsqrt_(float x) { return __builtin_amdgcn_rsqf(
 // ---------------------------------------------------------------------------
 // Anisotropy functions (Sec. 4.1): value a and gradient G of the polynomial in n.
 // ---------------------------------------------------------------------------
-template <class T>
-__host__ __device__ __forceinline__ void aniso_eval(const AnisoDev &A, T nx, T ny, T nz, T &a, T &Gx, T &Gy,
+template <class T, class E>
+__host__ __device__ __forceinline__ void aniso_eval(const E &A, T nx, T ny, T nz, T &a, T &Gx, T &Gy,
                                                     T &Gz) {
   Gx = Gy = Gz = T(0);
   if (A.kind == K_SECTORAL) {
@@ -310,8 +313,8 @@ __host__ __device__ __forceinline__ void aniso_eval(const AnisoDev &A, T nx, T n
 
 // An entry at direction n: the polynomial at m = R n, and by the chain rule
 // the gradient with respect to n, R^T (grad A)(m).
-template <class T>
-__host__ __device__ __forceinline__ void aniso_eval_rot(const AnisoDev &A, T nx, T ny, T nz, T &a, T &Gx, T &Gy,
+template <class T, class E>
+__host__ __device__ __forceinline__ void aniso_eval_rot(const E &A, T nx, T ny, T nz, T &a, T &Gx, T &Gy,
                                                         T &Gz) {
   if (!A.rot) {
     aniso_eval<T>(A, nx, ny, nz, a, Gx, Gy, Gz);
@@ -333,8 +336,12 @@ __host__ __device__ __forceinline__ void aniso_eval_rot(const AnisoDev &A, T nx,
 // (Eqs. Def_Normal_Vector, TermesAnisotropes).  Isotropic where |p| <= 1e-8
 // (lattice units): below that the direction of p is set by the rounding of
 // phi differences rather than by an interface, and a_s depends on it at O(eps).
-template <class T>
-__device__ __forceinline__ void flux(const AnisoDev *A, T px, T py, T pz, T &a, T &Nx, T &Ny, T &Nz) {
+// E is AnisoDev, or AnisoDev in the constant address space (ConstAniso) when
+// every lane reads the same entry: its reads are then scalar loads at the
+// point of use (through a generic pointer they are vector loads, each followed
+// by a wait for every load in flight).
+template <class T, class E>
+__device__ __forceinline__ void flux(const E *A, T px, T py, T pz, T &a, T &Nx, T &Ny, T &Nz) {
   a = T(1);
   Nx = Ny = Nz = T(0);
   if (A == nullptr || A->kind == K_ISO) return;

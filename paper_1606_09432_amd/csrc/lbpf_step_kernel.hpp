@@ -169,13 +169,6 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       m1 = min(m0 + tc.chunk, sd.nm);
     }
     const int per = sd.periodic;
-    // Without the index field every node takes the one anisotropy entry: read it
-    // here, before the first store of the launch, so that its reads are scalar
-    // and no node waits on a memory read for it.  (Read later from memory, each
-    // read is a vector load followed by a wait for every load in flight,
-    // prefetches included.)
-    AnisoDev a_one{};
-    if constexpr (!IDS) a_one = *sd.aniso;
     // mirror planes through node 0 can be reached only by tiles whose rings,
     // gathers and pulls go below node 3 of an axis (ring halo GR + 1 at most);
     // every other tile skips the mirror rules (a uniform branch), whose flags
@@ -495,9 +488,11 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       }
       const T un = OFF ? us_self + usum * T(1.0 / SC) : usum;
       // a_s, N, relaxation and source
-      const AnisoDev *A = IDS ? (idn > 0 ? sd.aniso + idn : nullptr) : &a_one;
       T a, Nx, Ny, Nz;
-      flux<T>(A, p0, p1, p2, a, Nx, Ny, Nz);
+      if constexpr (IDS)
+        flux<T>(idn > 0 ? sd.aniso + idn : nullptr, p0, p1, p2, a, Nx, Ny, Nz);
+      else  // one entry for every node
+        flux<T>((ConstAniso *)sd.aniso, p0, p1, p2, a, Nx, Ny, Nz);
       const T a2 = a * a;
       const T kph = pick<T>(sd.kphi, sd.kphi_f);
       const T om_ = rcp(a2 * kph + T(0.5));
