@@ -484,7 +484,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
         } else {
           fd[i] = kvv;
         }
-        usum += fd[i];
+        usum = (i == 0) ? fd[0] : usum + fd[i];
       }
       const T un = OFF ? us_self + usum * T(1.0 / SC) : usum;
       // a_s, N, relaxation and source
@@ -529,15 +529,23 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       }
     };
 
-    // component of Kc (offsets) or C (FP64) along direction i of the phi lattice
-    auto eC = [&](int i, int ps, int node) -> T {
+    // base + the component of Kc (offsets) or C (FP64) along direction i of the
+    // phi lattice.  The sum starts from the first nonzero term: adding a term
+    // to +0 is not an identity in IEEE arithmetic (-0 + 0 = +0), so the
+    // compiler would keep that addition as an instruction.
+    auto addEC = [&](int i, int ps, int node, T base) -> T {
       T v = T(0);
-      if (LP::E[i][0] != 0) v += T(LP::E[i][0]) * parS[ps][2][node];
-      if (LP::E[i][1] != 0) v += T(LP::E[i][1]) * parS[ps][3][node];
-      if constexpr (DIM == 3) {
-        if (LP::E[i][2] != 0) v += T(LP::E[i][2]) * parS[ps][4][node];
-      }
-      return v;
+      bool any = false;
+      auto term = [&](int c, int k) {
+        if (c == 0) return;
+        const T t = T(c) * parS[ps][k][node];
+        v = any ? v + t : t;
+        any = true;
+      };
+      term(LP::E[i][0], 2);
+      term(LP::E[i][1], 3);
+      if constexpr (DIM == 3) term(LP::E[i][2], 4);
+      return any ? base + v : base;
     };
 
     const int gx_o = x0 + tx;
@@ -636,10 +644,10 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
             //   = M h(y) + A' h(x) + w_i (K0 + e_i.Kc - SC phi(y)/a^2(x))
             const T Mc = parS[ps][0][node];
             const T Ap = parS[ps][1][node];
-            const T t = scphy * (Mc - T(1)) + (parS[ps][NP - 1][node] + eC(i, ps, node));
+            const T t = scphy * (Mc - T(1)) + addEC(i, ps, node, parS[ps][NP - 1][node]);
             d[i] = Mc * gy_ + (T(LP::W[i]) * t + Ap * gx_);
           } else {
-            const T gs = parS[ps][0][node] * gx_ + T(LP::W[i]) * (parS[ps][1][node] + eC(i, ps, node));
+            const T gs = parS[ps][0][node] * gx_ + T(LP::W[i]) * addEC(i, ps, node, parS[ps][1][node]);
             d[i] = gy_ + parS[ps][NP - 1][node] * (gs - gy_);
           }
         }
@@ -678,18 +686,18 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
           T loc;
           if constexpr (OFF)
             loc = a2o * (parS[sc][1][nodeo] * ST::ld(&gy_r[j]) +
-                         T(LP::W[j]) * (parS[sc][NP - 1][nodeo] + eC(j, sc, nodeo))) -
+                         T(LP::W[j]) * addEC(j, sc, nodeo, parS[sc][NP - 1][nodeo])) -
                   T(LP::W[j]) * scphy;
           else
-            loc = parS[sc][0][nodeo] * ST::ld(&gy_r[j]) + T(LP::W[j]) * (parS[sc][1][nodeo] + eC(j, sc, nodeo));
+            loc = parS[sc][0][nodeo] * ST::ld(&gy_r[j]) + T(LP::W[j]) * addEC(j, sc, nodeo, parS[sc][1][nodeo]);
           dn[i] = unk[i] ? (unk[j] ? loc : d[j]) : d[i];
         }
   #pragma unroll
         for (int i = 0; i < QP; ++i) d[i] = dn[i];
       }
-      T sum = T(0);
+      T sum = d[0];  // (not 0 + d[0]: see addEC)
   #pragma unroll
-      for (int i = 0; i < QP; ++i) sum += d[i];
+      for (int i = 1; i < QP; ++i) sum += d[i];
       const T phn = OFF ? phy + sum * T(1.0 / SC) : sum;
       if constexpr (OFF) {
         // the offsets of a node sum to zero. With COMP the rest offset is stored
@@ -701,7 +709,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
         for (int i = 1; i < QP; ++i) {
           const S q = ST::enc(d[i] - T(LP::W[i]) * sum);
           nt_store(reinterpret_cast<S *>(reinterpret_cast<char *>(gofield(i)) + iyb), q);
-          rsum += ST::dec(q);
+          rsum = (i == 1) ? ST::dec(q) : rsum + ST::dec(q);
         }
         ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(gofield(0)) + iyb),
                ST::COMP ? -rsum : d[0] - T(LP::W[0]) * sum);
@@ -723,7 +731,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
         for (int i = 1; i < QU; ++i) {
           const S q = ST::enc(keep * (fd_cur[i] - T(LU::W[i] * SC) * Sm));
           nt_store(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(i)) + iyb), q);
-          rsum += ST::dec(q);
+          rsum = (i == 1) ? ST::dec(q) : rsum + ST::dec(q);
         }
         ST::st(reinterpret_cast<S *>(reinterpret_cast<char *>(fofield(0)) + iyb),
                ST::COMP ? -rsum : keep * (fd_cur[0] - T(LU::W[0] * SC) * Sm));
