@@ -595,15 +595,25 @@ def cpu_baseline(cfg_full, sample_n: int, sample_steps: int):
 
 
 def cpu_model() -> str:
-    """The host CPU's model name (what lscpu prints as 'Model name')."""
+    """The host CPU's model name (what lscpu prints as 'Model name'), with the
+    family / model / stepping numbers, which identify it where a virtualised
+    host reports only a generic name."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.lower().startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = line.split(":", 1)
+                info.setdefault(k.strip().lower(), v.strip())
+            if not line.strip() and info:
+                break
     except OSError:
         pass
-    import platform
-    return platform.processor() or "unknown"
+    name = info.get("model name")
+    if not name:
+        import platform
+        name = platform.processor() or "unknown"
+    ids = [f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info]
+    return f"{name} ({', '.join(ids)})" if ids else name
 
 
 # -- rocprofv3 summaries ---------------------------------------------------------
