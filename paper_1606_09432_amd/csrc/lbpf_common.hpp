@@ -207,11 +207,37 @@ struct AnisoDev {
 // An entry read through the constant address space (the step never writes the
 // table).
 using ConstAniso = const __attribute__((address_space(4))) AnisoDev;
+
+// An entry of the crystal-index table staged in LDS by the step kernel, in the
+// arithmetic type T only (both field names of AnisoDev name the one value).
+template <class T> struct StagedAniso {
+  int kind, q, rot;
+  union { T R[9]; T Rf[9]; };
+  union { T eps; T epsf; };
+  union { T cr; T crf; };
+  union { T ci; T cif; };
+  union { T c0; T c0f; };
+  union { T c1; T c1f; };
+  union { T c2; T c2f; };
+};
 template <class T> __host__ __device__ __forceinline__ T pick(double d, float f) {
   if constexpr (sizeof(T) == sizeof(float))
     return f;
   else
     return d;
+}
+
+template <class T> __device__ __forceinline__ void stage_entry(const AnisoDev &a, StagedAniso<T> &s) {
+  s.kind = a.kind;
+  s.q = a.q;
+  s.rot = a.rot;
+  for (int k = 0; k < 9; ++k) s.R[k] = pick<T>(a.R[k], a.Rf[k]);
+  s.eps = pick<T>(a.eps, a.epsf);
+  s.cr = pick<T>(a.cr, a.crf);
+  s.ci = pick<T>(a.ci, a.cif);
+  s.c0 = pick<T>(a.c0, a.c0f);
+  s.c1 = pick<T>(a.c1, a.c1f);
+  s.c2 = pick<T>(a.c2, a.c2f);
 }
 constexpr int kMaxAniso = 256;
 
@@ -336,7 +362,8 @@ __host__ __device__ __forceinline__ void aniso_eval_rot(const E &A, T nx, T ny, 
 // (Eqs. Def_Normal_Vector, TermesAnisotropes).  Isotropic where |p| <= 1e-8
 // (lattice units): below that the direction of p is set by the rounding of
 // phi differences rather than by an interface, and a_s depends on it at O(eps).
-// E is AnisoDev, or AnisoDev in the constant address space (ConstAniso) when
+// E is StagedAniso<T> (an index table staged in LDS), or AnisoDev, or
+// AnisoDev in the constant address space (ConstAniso) when
 // every lane reads the same entry: its reads are then scalar loads at the
 // point of use (through a generic pointer they are vector loads, each followed
 // by a wait for every load in flight).

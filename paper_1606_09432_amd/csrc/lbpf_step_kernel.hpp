@@ -85,9 +85,13 @@ template <class E> __device__ __forceinline__ void stb(E *base, unsigned boff, E
   nt_store(reinterpret_cast<E *>(reinterpret_cast<char *>(base) + boff), v);
 }
 
-// Minimum waves per SIMD the register allocator must leave room for.
-template <int DIM, int TY, class ST> constexpr int min_waves() {
-  return DIM == 2 ? (std::is_same<ST, StF64>::value ? 3 : 5) : (std::is_same<ST, StF64>::value ? 2 : (TY == 8 ? 4 : 3));
+// Largest crystal-index table staged in LDS (FP32-arithmetic forms).
+constexpr int kStagedAniso = 32;
+
+// Minimum waves per SIMD the register allocator must leave room for (2D
+// kernels with the index field: 4, which they fit without spills).
+template <int DIM, int TY, class ST, bool IDS> constexpr int min_waves() {
+  return DIM == 2 ? (std::is_same<ST, StF64>::value ? 3 : (IDS ? 4 : 5)) : (std::is_same<ST, StF64>::value ? 2 : (TY == 8 ? 4 : 3));
 }
 
 // BATCH = false: one simulation (sd_arg); the work-group id gives the tile and
@@ -104,7 +108,7 @@ template <int DIM, int TY, class ST> constexpr int min_waves() {
 // Sec. 4.2 through the moment of Eq. Grad_DF-Centree; the gradient then reaches
 // two nodes, so the phi ring keeps a 3-node halo and one more plane.
 template <int K, int TY, class ST, bool IDS, bool BATCH, bool MIR, int GR>
-__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(min_waves<LatOf<K>::DIM, TY, ST>(), 8))) void
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(min_waves<LatOf<K>::DIM, TY, ST, IDS>(), 8))) void
 step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const BatchItem *__restrict__ items,
             int n_items) {
   constexpr int DIM = LatOf<K>::DIM;
@@ -141,6 +145,11 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
   __shared__ float usS[OFF ? NRU : 1][OFF ? PLANE_F : 1];
   __shared__ int16_t idS[IDS ? NRU : 1][IDS ? PLANE_F : 1];
   __shared__ T parS[3][NP][PLANE_P];
+  // the crystal-index table of the FP32-arithmetic forms, staged in LDS when it
+  // has at most kStagedAniso entries: a node's entry is then an LDS read, not
+  // a vector load followed by a wait for every load in flight
+  constexpr bool STAGE = IDS && OFF;
+  __shared__ StagedAniso<T> tabS[STAGE ? kStagedAniso : 1];
 
   for (int it = blockIdx.x; !BATCH || it < n_items; it += gridDim.x) {
     const int tx = threadIdx.x;
@@ -169,6 +178,13 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       m1 = min(m0 + tc.chunk, sd.nm);
     }
     const int per = sd.periodic;
+    const bool staged = STAGE && sd.n_aniso <= kStagedAniso;
+    if (staged) {
+      // visible to every wave after the warm-up barrier below (in an ensemble
+      // the item's opening barrier keeps the previous item's readers apart)
+      for (int k = threadIdx.x + ((DIM == 3) ? threadIdx.y * TX : 0); k < sd.n_aniso; k += NT)
+        stage_entry<T>(sd.aniso[k], tabS[k]);
+    }
     // mirror planes through node 0 can be reached only by tiles whose rings,
     // gathers and pulls go below node 3 of an axis (ring halo GR + 1 at most);
     // every other tile skips the mirror rules (a uniform branch), whose flags
@@ -489,10 +505,14 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       const T un = OFF ? us_self + usum * T(1.0 / SC) : usum;
       // a_s, N, relaxation and source
       T a, Nx, Ny, Nz;
-      if constexpr (IDS)
-        flux<T>(idn > 0 ? sd.aniso + idn : nullptr, p0, p1, p2, a, Nx, Ny, Nz);
-      else  // one entry for every node
+      if constexpr (IDS) {
+        if (staged)
+          flux<T>(idn > 0 ? &tabS[idn] : nullptr, p0, p1, p2, a, Nx, Ny, Nz);
+        else
+          flux<T>(idn > 0 ? sd.aniso + idn : nullptr, p0, p1, p2, a, Nx, Ny, Nz);
+      } else {  // one entry for every node
         flux<T>((ConstAniso *)sd.aniso, p0, p1, p2, a, Nx, Ny, Nz);
+      }
       const T a2 = a * a;
       const T kph = pick<T>(sd.kphi, sd.kphi_f);
       const T om_ = rcp(a2 * kph + T(0.5));
