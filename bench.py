@@ -224,6 +224,44 @@ def run_batched(steps: int, warmup: int):
                          "bytes_per_node_step": b_alg}}
 
 
+def run_c1_throughput(steps: int, grow: int = 1000):
+    """The twenty-crystal 2048^2 workload (its own four-fold orientation per
+    crystal in the index field), directional derivatives and central
+    differences advancing together as one batched pair, in FP64 and in
+    FP32-offset storage: MLUPS over `steps` steps after `grow` steps of growth
+    (rows per work item from the autotuner)."""
+    import torch
+
+    import paper_1606_09432_amd as lb
+    from paper_1606_09432_amd import workloads as W
+
+    out = {"workload": "2048^2 D2Q9/D2Q5, 20 crystals with their own orientation (index field, 21 entries), "
+                       "DD and CD as one batched pair", "steps": steps, "after_steps": grow}
+    for st in ("fp64", "fp32"):
+        cfgs = [W.c1(st, g) for g in ("dd", "cd")]
+        nodes = sum(c.nodes for c in cfgs)
+        sim = lb.Simulation(cfgs)
+        sim.autotune(4)
+        sim.step(grow)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream()
+        e0.record(stream)
+        sim.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        tile = sim.get_tile()
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        out[st] = {"value": nodes / (ms * 1e-3) / 1e6, "unit": "MLUPS", "ms_per_step": ms, "chunk": tile[1]}
+        print(f"[bench] c1 {st}: {ms:.3f} ms/step  {out[st]['value']:.1f} MLUPS chunk={tile[1]}", file=sys.stderr,
+              flush=True)
+    return out
+
+
 def run_accuracy(workload: str, n: int, steps: int, every: int, variant: str):
     """Error of the FP32- and FP16-offset forms against the FP64 form (itself
     checked against the FP64 oracle) over a run: max |d phi|, max |d u|,
@@ -681,6 +719,10 @@ def summarize_trace(d, command, bench_json=None):
         for st, r in b.get("d3q15", {}).items():
             out.append(f"- D3Q15 {st}: {r['ms_per_step']:.4f} ms, {r['value']:.1f} {r['unit']}, "
                        f"{r['roofline']['achieved']:.0f} GB/s algorithmic")
+        for st in ("fp64", "fp32"):
+            r = b.get("c1", {}).get(st)
+            if r:
+                out.append(f"- C1 pair (2048^2, index field) {st}: {r['ms_per_step']:.4f} ms, {r['value']:.1f} MLUPS")
         for st in ("fp16", "fp64"):
             r = b.get("dense", {}).get(st)
             if r:
@@ -966,6 +1008,7 @@ def main():
                                 "anisotropic_fraction": rr["anisotropic_fraction"]}
     if not args.no_batched and not args.only:
         out["batched"] = run_batched(args.steps, args.warmup)
+        out["c1"] = run_c1_throughput(min(args.steps, 500))
     if not args.no_d3q15 and not args.only:
         # the paper's own 3D phase-field lattice on the same workload
         out["d3q15"] = {}

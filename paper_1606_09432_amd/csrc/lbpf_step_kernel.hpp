@@ -85,7 +85,7 @@ template <class E> __device__ __forceinline__ void stb(E *base, unsigned boff, E
   nt_store(reinterpret_cast<E *>(reinterpret_cast<char *>(base) + boff), v);
 }
 
-// Largest crystal-index table staged in LDS (FP32-arithmetic forms).
+// Largest crystal-index table staged in LDS.
 constexpr int kStagedAniso = 32;
 
 // Minimum waves per SIMD the register allocator must leave room for (2D
@@ -145,10 +145,10 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
   __shared__ float usS[OFF ? NRU : 1][OFF ? PLANE_F : 1];
   __shared__ int16_t idS[IDS ? NRU : 1][IDS ? PLANE_F : 1];
   __shared__ T parS[3][NP][PLANE_P];
-  // the crystal-index table of the FP32-arithmetic forms, staged in LDS when it
-  // has at most kStagedAniso entries: a node's entry is then an LDS read, not
-  // a vector load followed by a wait for every load in flight
-  constexpr bool STAGE = IDS && OFF;
+  // the crystal-index table, staged in LDS in the arithmetic type when it has at
+  // most kStagedAniso entries: a node's entry is then an LDS read, not a vector
+  // load followed by a wait for every load in flight
+  constexpr bool STAGE = IDS;
   __shared__ StagedAniso<T> tabS[STAGE ? kStagedAniso : 1];
 
   for (int it = blockIdx.x; !BATCH || it < n_items; it += gridDim.x) {
