@@ -781,9 +781,16 @@ def summarize_traffic(fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_bytes, 
         if lat is None or st is None or f is None or w is None:
             continue
         if lat == "D2Q9_D2Q5":
-            if len(targs) < 5 or targs[4] != "true" or st != "fp32":
+            # batched instances: without the index field the C4 ensemble (FP32),
+            # with it the twenty-crystal pair (FP64 and FP32)
+            if len(targs) < 5 or targs[4] != "true":
                 continue
-            st, nodes = BATCHED_KEY, ens_nodes
+            if targs[3] == "false" and st == "fp32":
+                st, nodes = BATCHED_KEY, ens_nodes
+            elif targs[3] == "true" and st in ("fp32", "fp64"):
+                st, nodes = f"c1_pair_{st}", 2 * 2048 * 2048
+            else:
+                continue
         else:
             st, nodes = traffic_key(lat, st), 512 ** 3
         rb, wb = f * ff, w * fw
