@@ -292,6 +292,23 @@ def test_3d_crystal_index_offset_storage(gpu, oracle_mod, storage, tol):
     assert int(near.sum()) == 0 and int(diff.sum()) <= cfg.nodes // 1000
 
 
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_large_index_table_parity(gpu, oracle_mod, case):
+    """More crystal entries than the kernel stages in LDS (32): the entries are
+    then read from the table in memory; FP64 against the oracle."""
+    if case == "2d":
+        cfg = W.c1(n=256, count=40)
+        steps = 150
+    else:
+        base = W.oriented_3d(shape=(48, 44, 40))
+        extra = [W.Aniso("iso")] * 38  # unused entries beyond the staged range
+        cfg = base.replace(aniso=list(base.aniso) + extra)
+        steps = 40
+    assert len(cfg.aniso) > 32
+    sim, orc = _compare(gpu, oracle_mod, cfg, steps)
+    assert np.array_equal(sim.fields()[2].cpu().numpy(), orc.ids())
+
+
 def test_batched_with_index_field(gpu, oracle_mod):
     """A batched ensemble whose members use the crystal index field."""
     cfgs = [W.c1(n=n, count=3, rng_seed=s).replace(ny=n + 16) for n, s in ((96, 1), (128, 2), (80, 3))]
