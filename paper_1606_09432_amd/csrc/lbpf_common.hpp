@@ -371,9 +371,11 @@ template <class T, class E>
 __device__ __forceinline__ void flux(const E *A, T px, T py, T pz, T &a, T &Nx, T &Ny, T &Nz) {
   a = T(1);
   Nx = Ny = Nz = T(0);
-  if (A == nullptr || A->kind == K_ISO) return;
+  if (A == nullptr) return;
+  // the cutoff first: away from interfaces no lane of a wave reads the entry
   const T r2 = (px * px + py * py) + pz * pz;
   if (!(r2 > T(1e-16))) return;
+  if (A->kind == K_ISO) return;
   const T ir = rsqrt_(r2);
   const T r = r2 * ir;
   const T nx = -px * ir, ny = -py * ir, nz = -pz * ir;
