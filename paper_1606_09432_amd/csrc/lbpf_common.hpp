@@ -146,6 +146,14 @@ template <class E> __device__ __forceinline__ void nt_store(E *p, E v) {
 // 1.5e-8) stay above the FP16 subnormal range; |offsets| stay far below
 // 65504 / 2^12 = 16.  A power of two scales without rounding.  The step folds
 // SC into its compile-time weights, so the scale costs no instruction.
+// FOLD_3D: the 3D offset pulls read coefficients with 1/a^2 folded in (M, A',
+// Kc, K0) rather than (A, B, C, 1/a^2) and phi of the source node;
+// HEAT_CONST_3D: a 3D node whose heat sources all lie inside the box takes their
+// ring offsets as constants.  The 2D forms always do both.  Either form computes
+// the same quantities up to rounding order; each is set where it measured
+// faster (the offset steps are bound by their instruction stream and register
+// schedule, which both change: FP16 3D is 2-4% faster without either, FP32 3D
+// 1-5% faster with both, 2D FP16 8% faster with both).
 struct StF64 {
   using T = double;  // arithmetic
   using S = double;  // stored distribution
@@ -153,6 +161,8 @@ struct StF64 {
   static constexpr bool OFF = false;
   static constexpr bool COMP = false;
   static constexpr double SC = 1.0;
+  static constexpr bool FOLD_3D = false;
+  static constexpr bool HEAT_CONST_3D = false;
   static __device__ __forceinline__ T ld(const S *p) { return *p; }
   static __device__ __forceinline__ void st(S *p, T v) { nt_store(p, S(v)); }
   static __device__ __forceinline__ S enc(T v) { return v; }
@@ -165,6 +175,8 @@ struct StF32 {
   static constexpr bool OFF = true;
   static constexpr bool COMP = false;
   static constexpr double SC = 1.0;
+  static constexpr bool FOLD_3D = true;
+  static constexpr bool HEAT_CONST_3D = true;
   static __device__ __forceinline__ T ld(const S *p) { return *p; }
   static __device__ __forceinline__ void st(S *p, T v) { nt_store(p, S(v)); }
   static __device__ __forceinline__ S enc(T v) { return v; }
@@ -178,6 +190,8 @@ struct StF16 {
   // the rest offset balances the rounded others (FP16 rounding is coarse)
   static constexpr bool COMP = true;
   static constexpr double SC = 4096.0;
+  static constexpr bool FOLD_3D = false;
+  static constexpr bool HEAT_CONST_3D = false;
   static __device__ __forceinline__ T ld(const S *p) { return __half2float(*p); }
   static __device__ __forceinline__ void st(S *p, T v) { nt_store(p, __float2half_rn(v)); }
   static __device__ __forceinline__ S enc(T v) { return __float2half_rn(v); }

@@ -135,6 +135,8 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
   constexpr int NRU = GR + 3;                      // u* and index ring planes
   constexpr int QP = LP::Q, QU = LU::Q;
   constexpr bool OFF = ST::OFF;
+  constexpr bool FOLD = OFF && (DIM == 2 || ST::FOLD_3D);
+  constexpr bool HEAT_CONST = DIM == 2 || ST::HEAT_CONST_3D;
   // offsets (h, k, and the pulled d and gathered fd of the offset forms) are
   // kept in stored units: SC per true unit; true-unit terms entering them are
   // scaled through the weights (compile-time constants)
@@ -473,7 +475,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       T usum = T(0);
       // the node's heat sources all lie inside the box (and beyond no plane):
       // each sits at the ring offset -e_i, a constant
-      const bool inner = xy_in2 && pm >= 1 && pm + 1 < sd.nm;
+      const bool inner = HEAT_CONST && xy_in2 && pm >= 1 && pm + 1 < sd.nm;
   #pragma unroll
       for (int i = 0; i < QU; ++i) {
         const T kvv = T(kv[i]);
@@ -521,7 +523,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       const T cC = -om_ * kph;
       const int node = hy * HX + hx;
       const T ia2 = rcp(a2);
-      if constexpr (OFF) {
+      if constexpr (FOLD) {
         // what a pull from this node needs, with 1/a^2 folded in:
         //   M = 1 - 1/a^2, A' = (1 - w)/a^2, Kc = SC cC N / a^2, K0 = SC (phi + Q s)/a^2
         const T kc = T(SC) * ia2 * cC;
@@ -532,9 +534,9 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
         if constexpr (DIM == 3) parS[ps][4][node] = kc * Nz;
         parS[ps][NP - 1][node] = (T(SC) * ia2) * (phc + Qs);
       } else {
-        // FP64: A = 1 - w, B = w phi + Q s, C = cC N and 1/a^2
+        // A = 1 - w, B = w phi + Q s (offsets: Q s), C = cC N and 1/a^2
         parS[ps][0][node] = T(1) - om_;
-        parS[ps][1][node] = om_ * phc + Qs;
+        parS[ps][1][node] = OFF ? Qs : om_ * phc + Qs;
         parS[ps][2][node] = cC * Nx;
         parS[ps][3][node] = cC * Ny;
         if constexpr (DIM == 3) parS[ps][4][node] = cC * Nz;
@@ -659,13 +661,19 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
           const int node = nodeo - cy * HX - cx;
           const T gy_ = ST::ld(&gy_r[i]);
           const T gx_ = ST::ld(&gx_r[i]);
-          if constexpr (OFF) {
+          if constexpr (FOLD) {
             // d = h(y) + [h*(x) + w_i (phi(x) - phi(y)) - h(y)]/a^2(x)
             //   = M h(y) + A' h(x) + w_i (K0 + e_i.Kc - SC phi(y)/a^2(x))
             const T Mc = parS[ps][0][node];
             const T Ap = parS[ps][1][node];
             const T t = scphy * (Mc - T(1)) + addEC(i, ps, node, parS[ps][NP - 1][node]);
             d[i] = Mc * gy_ + (T(LP::W[i]) * t + Ap * gx_);
+          } else if constexpr (OFF) {
+            // d = h(y) + [h*(x) + w_i SC (phi(x) - phi(y)) - h(y)]/a^2(x),
+            // h*(x) = A h(x) + w_i SC (B + e_i.C)
+            const T phx = phiS[rs(m - cm)][pco - cy * PX - cx];
+            const T hs = parS[ps][0][node] * gx_ + T(LP::W[i] * SC) * addEC(i, ps, node, parS[ps][1][node]);
+            d[i] = gy_ + parS[ps][NP - 1][node] * (T(LP::W[i] * SC) * (phx - phy) + hs - gy_);
           } else {
             const T gs = parS[ps][0][node] * gx_ + T(LP::W[i]) * addEC(i, ps, node, parS[ps][1][node]);
             d[i] = gy_ + parS[ps][NP - 1][node] * (gs - gy_);
@@ -697,19 +705,20 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       if (walls) {
         // bounce-back: an unknown incoming population takes the opposite one; if
         // that is unknown too, the local post-collision opposite population
-        // (offsets: h*_j(y) = a^2 [A' h_j(y) + w_j (K0 + e_j.Kc)] - w_j SC phi(y))
+        // (folded offsets: h*_j(y) = a^2 [A' h_j(y) + w_j (K0 + e_j.Kc)] - w_j SC phi(y);
+        // otherwise h*_j(y) = A h_j(y) + w_j SC (B + e_j.C))
         T dn[QP];
-        const T a2o = OFF ? rcp(T(1) - parS[sc][0][nodeo]) : T(0);
+        const T a2o = FOLD ? rcp(T(1) - parS[sc][0][nodeo]) : T(0);
   #pragma unroll
         for (int i = 0; i < QP; ++i) {
           const int j = LP::OPP[i];
           T loc;
-          if constexpr (OFF)
+          if constexpr (FOLD)
             loc = a2o * (parS[sc][1][nodeo] * ST::ld(&gy_r[j]) +
                          T(LP::W[j]) * addEC(j, sc, nodeo, parS[sc][NP - 1][nodeo])) -
                   T(LP::W[j]) * scphy;
-          else
-            loc = parS[sc][0][nodeo] * ST::ld(&gy_r[j]) + T(LP::W[j]) * addEC(j, sc, nodeo, parS[sc][1][nodeo]);
+          else  // (SC is 1 for FP64)
+            loc = parS[sc][0][nodeo] * ST::ld(&gy_r[j]) + T(LP::W[j] * SC) * addEC(j, sc, nodeo, parS[sc][1][nodeo]);
           dn[i] = unk[i] ? (unk[j] ? loc : d[j]) : d[i];
         }
   #pragma unroll
