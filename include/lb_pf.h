@@ -178,7 +178,12 @@ int lb_pf_init(const lbpf_config *cfgs, int n_sims, void *dev_workspace, size_t 
                void *hip_stream, lbpf_handle **out);
 
 /* Enqueues n_steps coupled steps (phase field, then heat) for every
- * simulation of the handle.  One fused kernel launch per step.  A batched
+ * simulation of the handle.  One fused kernel launch per step; a box with
+ * mirror planes (LBPF_MIRROR_LOW, not batched) whose tiling leaves tiles beyond
+ * the planes' reach takes two concurrent launches instead: the tiles at a plane
+ * on a stream of the handle's own, forked from and joined back to hip_stream
+ * with events, and the others on hip_stream, so that work enqueued on
+ * hip_stream afterwards sees the whole step.  A batched
  * handle advances all its simulations in one persistent launch per step over
  * a work list of (simulation, 64-wide column, rows) items, replayed from HIP
  * graphs of 1 and 8 steps that are captured, on a private stream, the first
@@ -259,7 +264,8 @@ int lb_pf_info(const lbpf_handle *h, int sim, int64_t *nodes, int64_t *step, int
 
 /* Frees the handle (not the workspace).  Work enqueued on the handle must be
  * complete, except for a batched handle, whose destruction waits for the
- * device because its graphs may still run. */
+ * device because its graphs may still run (the handle's own stream of a
+ * mirror box is synchronised before it is destroyed). */
 int lb_pf_destroy(lbpf_handle *h);
 const char *lb_pf_last_error(void);
 

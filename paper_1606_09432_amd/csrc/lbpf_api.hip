@@ -85,7 +85,24 @@ struct lbpf_handle {
   int64_t step = 0;
   int device = 0;  // the device current at lb_pf_init
   BatchState batch;
+  // boxes with mirror planes: the tiles at a plane run on `aux`, concurrently
+  // with the others on the caller's stream (events fork and join order them)
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
+
+namespace {
+void release_aux(lbpf_handle *h) {
+  if (h->aux) {
+    hipStreamSynchronize(h->aux);
+    hipStreamDestroy(h->aux);
+  }
+  if (h->fork) hipEventDestroy(h->fork);
+  if (h->join) hipEventDestroy(h->join);
+  h->aux = nullptr;
+  h->fork = h->join = nullptr;
+}
+}  // namespace
 
 // Scratch of lb_pf_diagnostics_noalloc: the per-block partials and the result
 // of the diagnostics reductions, in a file-scope device array instead of the
@@ -609,6 +626,19 @@ int lb_pf_init(const lbpf_config *cfgs, int n_sims, void *dev_workspace, size_t 
       return fail(LBPF_ERR_HIP, std::string("batched set-up failed: ") + hipGetErrorString(e));
     }
     build_items(h->sims, b);
+  } else {
+    bool any_mirror = false;
+    for (const SimHost &s : h->sims) any_mirror = any_mirror || s.cfg.boundary == LBPF_MIRROR_LOW;
+    if (any_mirror) {
+      hipError_t e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&h->fork, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&h->join, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        release_aux(h);
+        delete h;
+        return fail(LBPF_ERR_HIP, std::string("mirror-box stream set-up failed: ") + hipGetErrorString(e));
+      }
+    }
   }
   *out = h;
   return LBPF_OK;
@@ -695,6 +725,29 @@ int batch_step(lbpf_handle *h, int n_steps, hipStream_t st) {
   return LBPF_OK;
 }
 
+
+// One step of simulation s.  A box with mirror planes whose tiling leaves
+// tiles beyond the mirror rules' reach runs them with the instance without
+// mirror planes (fewer registers and instructions) on st, and the tiles at a
+// plane with the mirror instance on the handle's aux stream, concurrently;
+// st then waits for both.  Either way every node is written once.
+hipError_t step_sim(lbpf_handle *h, const SimHost &s, const SimDev &d, hipStream_t st) {
+  const TileDev &t = s.tile;
+  const bool split = d.mirror && !d.grad_up2 && h->aux && t.chunk >= 4 && (s.dim == 2 || t.ty >= 4) &&
+                     t.tiles_x >= 2 && t.nchunks >= 2 && (s.dim == 2 || t.tiles_y >= 2);
+  if (!split) return launch_step(s.cfg.lattice, s.storage, d, t, st);
+  TileDev at = t, rest = t;
+  at.part = 1;
+  rest.part = 2;
+  hipError_t e = hipEventRecord(h->fork, st);
+  if (e == hipSuccess) e = hipStreamWaitEvent(h->aux, h->fork, 0);
+  if (e == hipSuccess) e = launch_step(s.cfg.lattice, s.storage, d, at, h->aux);
+  if (e == hipSuccess) e = launch_step(s.cfg.lattice, s.storage, d, rest, st);
+  if (e == hipSuccess) e = hipEventRecord(h->join, h->aux);
+  if (e == hipSuccess) e = hipStreamWaitEvent(st, h->join, 0);
+  return e;
+}
+
 }  // namespace
 
 int lb_pf_step(lbpf_handle *h, int n_steps, void *hip_stream) {
@@ -705,7 +758,7 @@ int lb_pf_step(lbpf_handle *h, int n_steps, void *hip_stream) {
   for (int n = 0; n < n_steps; ++n) {
     for (const SimHost &s : h->sims) {
       const SimDev d = make_dev(h, s, h->parity);
-      HIPCHK(launch_step(s.cfg.lattice, s.storage, d, s.tile, st));
+      HIPCHK(step_sim(h, s, d, st));
     }
     h->parity ^= 1;
     h->step++;
@@ -994,6 +1047,7 @@ int lb_pf_destroy(lbpf_handle *h) {
     drop_graphs(b);
     hipStreamDestroy(b.cap);
   }
+  release_aux(h);
   delete h;
   return LBPF_OK;
 }

@@ -9,10 +9,54 @@
 namespace lbpf {
 
 // Tiling of the step kernel: tiles_x x tiles_y tiles of 64 x ty nodes, each
-// marching `chunk` planes; nchunks = ceil(extent along m / chunk).
+// marching `chunk` planes; nchunks = ceil(extent along m / chunk).  part
+// selects the work items of one launch: 0 every one; in a box with mirror
+// planes through node 0, 1 those at a plane (tile x 0, tile y 0 in 3D, chunk
+// 0) and 2 all others (which the mirror rules do not reach when ty >= 4 in 3D
+// and chunk >= 4: their rings start at node 4 or beyond along every axis).
 struct TileDev {
-  int tiles_x, tiles_y, nchunks, chunk, ty;
+  int tiles_x, tiles_y, nchunks, chunk, ty, part;
 };
+
+// Work-groups of a launch over part t.part of the tiles (ydir: tile y 0 lies
+// at a plane, i.e. 3D).
+__host__ __device__ inline long long part_blocks(const TileDev &t, bool ydir) {
+  const long long all = (long long)t.tiles_x * t.tiles_y * t.nchunks;
+  const long long inner = (long long)(t.tiles_x - 1) * (t.tiles_y - (ydir ? 1 : 0)) * (t.nchunks - 1);
+  return t.part == 0 ? all : (t.part == 2 ? inner : all - inner);
+}
+
+// Tile (x, y) and chunk c of work-group L of a launch over part 1 or 2.
+// Part 1 lists the slab of tile x 0 (every y, every chunk), then in 3D the
+// slab of tile y 0 (x >= 1, every chunk), then chunk 0 of the remaining tiles.
+__device__ inline void part_tile(const TileDev &t, bool ydir, int L, int &x, int &y, int &c) {
+  const int y0 = ydir ? 1 : 0;
+  const int nx1 = t.tiles_x - 1, ny1 = t.tiles_y - y0;
+  if (t.part == 2) {
+    x = 1 + L % nx1;
+    L /= nx1;
+    y = y0 + L % ny1;
+    c = 1 + L / ny1;
+    return;
+  }
+  const int a = t.tiles_y * t.nchunks;
+  const int b = ydir ? nx1 * t.nchunks : 0;
+  if (L < a) {
+    x = 0;
+    y = L % t.tiles_y;
+    c = L / t.tiles_y;
+  } else if (L < a + b) {
+    L -= a;
+    x = 1 + L % nx1;
+    y = 0;
+    c = L / nx1;
+  } else {
+    L -= a + b;
+    x = 1 + L % nx1;
+    y = y0 + L / nx1;
+    c = 0;
+  }
+}
 
 // One item of a batched step: rows m0 .. m1-1 of the 64-wide column at x0
 // of simulation `sim` (2D).

@@ -6,7 +6,8 @@ namespace lbpf {
 
 hipError_t launch_step(int lattice, int storage, const SimDev &sd, const TileDev &tc, hipStream_t st) {
   if (sd.grad_up2) return launch_step_up2(lattice, storage, sd, tc, st);
-  if (sd.mirror) return launch_step_mirror(lattice, storage, sd, tc, st);
+  // (part 2 of a box with mirror planes: tiles the mirror rules do not reach)
+  if (sd.mirror && tc.part != 2) return launch_step_mirror(lattice, storage, sd, tc, st);
   return launch_step_m<false>(lattice, storage, sd, tc, st);
 }
 

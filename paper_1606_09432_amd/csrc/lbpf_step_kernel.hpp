@@ -170,10 +170,15 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       __syncthreads();  // the previous item is done with the LDS rings
     } else {
       int L = xcd_remap(blockIdx.x, gridDim.x);
-      const int tile_x = L % tc.tiles_x;
-      L /= tc.tiles_x;
-      const int tile_y = L % tc.tiles_y;
-      const int chunk = L / tc.tiles_y;
+      int tile_x, tile_y, chunk;
+      if (tc.part == 0) {
+        tile_x = L % tc.tiles_x;
+        L /= tc.tiles_x;
+        tile_y = L % tc.tiles_y;
+        chunk = L / tc.tiles_y;
+      } else {
+        part_tile(tc, DIM == 3, L, tile_x, tile_y, chunk);
+      }
       x0 = tile_x * TX;
       y0 = (DIM == 3) ? tile_y * TY : 0;
       m0 = chunk * tc.chunk;
@@ -846,7 +851,8 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
 // ---- launchers, instantiated once per value of MIR (one source file each) ----
 template <int K, int TY, class ST, bool IDS, bool MIR, int GR = 1>
 static hipError_t launch_step_t(const SimDev &sd, const TileDev &tc, hipStream_t st) {
-  const int nblocks = tc.tiles_x * tc.tiles_y * tc.nchunks;
+  const int nblocks = (int)part_blocks(tc, LatOf<K>::DIM == 3);
+  if (nblocks == 0) return hipSuccess;
   dim3 block(64, LatOf<K>::DIM == 3 ? TY : 1);
   hipLaunchKernelGGL((step_kernel<K, TY, ST, IDS, false, MIR, GR>), dim3(nblocks), block, 0, st, sd, tc, nullptr,
                      nullptr, 0);

@@ -79,9 +79,11 @@ def test_mirror_3d_fp64_parity(gpu, oracle_mod, lattice, grad, shape, entry, ste
     _compare(gpu, oracle_mod, _mirror_3d(shape, lattice, grad, entry), steps)
 
 
-def test_mirror_3d_crystal_index_parity(gpu, oracle_mod):
-    # every entry symmetric about the planes (the library refuses others)
-    cfg = W.multi_3d(boundary="mirror_low", y66_phi0=0.0)
+@pytest.mark.parametrize("shape", [(48, 44, 40), (70, 30, 26)])
+def test_mirror_3d_crystal_index_parity(gpu, oracle_mod, shape):
+    # every entry symmetric about the planes (the library refuses others); the
+    # second box has tiles beyond the planes' reach (run by the plain instance)
+    cfg = W.multi_3d(boundary="mirror_low", y66_phi0=0.0, shape=shape)
     cfg = cfg.replace(seeds=[W.Seed(0, 0, 0, 5.0, 1)] + cfg.seeds[1:])
     _compare(gpu, oracle_mod, cfg, 60)
 
@@ -107,8 +109,11 @@ def test_mirror_offset_storage_accuracy(gpu, oracle_mod, storage, tol):
     _compare(gpu, oracle_mod, _mirror_2d(130, 67, storage=storage), 300, tol=tol)
 
 
-@pytest.mark.parametrize("storage,tiles", [("fp64", [(4, 8), (4, 64)]),
-                                           ("fp16", [(12, 32), (4, 7), (8, 64), (12, 5)])])
+# (4, 3) and (8, 3): chunks too short to leave chunk 1 beyond the planes' reach,
+# so every tile runs with the mirror instance; the others split the tiles
+# between the two instances
+@pytest.mark.parametrize("storage,tiles", [("fp64", [(4, 8), (4, 64), (4, 3)]),
+                                           ("fp16", [(12, 32), (4, 7), (8, 64), (12, 5), (8, 3)])])
 def test_mirror_tile_shapes_bitwise_equal(gpu, storage, tiles):
     cfg = _mirror_3d((70, 50, 45), storage=storage)
     _say(f"mirror tiles {storage} {tiles}")
