@@ -94,11 +94,11 @@ struct lbpf_handle {
 namespace {
 void release_aux(lbpf_handle *h) {
   if (h->aux) {
-    hipStreamSynchronize(h->aux);
-    hipStreamDestroy(h->aux);
+    (void)hipStreamSynchronize(h->aux);
+    (void)hipStreamDestroy(h->aux);
   }
-  if (h->fork) hipEventDestroy(h->fork);
-  if (h->join) hipEventDestroy(h->join);
+  if (h->fork) (void)hipEventDestroy(h->fork);
+  if (h->join) (void)hipEventDestroy(h->join);
   h->aux = nullptr;
   h->fork = h->join = nullptr;
 }
@@ -650,7 +650,7 @@ void drop_graphs(BatchState &b) {
   for (auto &row : b.exec)
     for (hipGraphExec_t &g : row)
       if (g) {
-        hipGraphExecDestroy(g);
+        (void)hipGraphExecDestroy(g);
         g = nullptr;
       }
 }
@@ -688,12 +688,12 @@ int batch_graph(lbpf_handle *h, int p, int kind) {
   hipGraph_t g = nullptr;
   hipError_t ee = hipStreamEndCapture(b.cap, &g);
   if (le != hipSuccess || ee != hipSuccess) {
-    if (g) hipGraphDestroy(g);
+    if (g) (void)hipGraphDestroy(g);
     return fail(LBPF_ERR_HIP, std::string("graph capture failed: ") +
                                   hipGetErrorString(le != hipSuccess ? le : ee));
   }
   hipError_t ie = hipGraphInstantiate(&b.exec[p][kind], g, nullptr, nullptr, 0);
-  hipGraphDestroy(g);
+  (void)hipGraphDestroy(g);
   if (ie != hipSuccess) {
     b.exec[p][kind] = nullptr;
     return fail(LBPF_ERR_HIP, std::string("graph instantiation failed: ") + hipGetErrorString(ie));
@@ -993,7 +993,7 @@ int lb_pf_autotune(lbpf_handle *h, int steps_per_trial, void *hip_stream) {
     hipEvent_t e[2] = {nullptr, nullptr};
     ~Events() {
       for (hipEvent_t x : e)
-        if (x) hipEventDestroy(x);
+        if (x) (void)hipEventDestroy(x);
     }
   } ev;
   HIPCHK(hipEventCreate(&ev.e[0]));
@@ -1043,9 +1043,9 @@ int lb_pf_destroy(lbpf_handle *h) {
   BatchState &b = h->batch;
   if (b.cap) {
     // graphs of this handle may still run on the caller's streams
-    hipDeviceSynchronize();
+    (void)hipDeviceSynchronize();
     drop_graphs(b);
-    hipStreamDestroy(b.cap);
+    (void)hipStreamDestroy(b.cap);
   }
   release_aux(h);
   delete h;
