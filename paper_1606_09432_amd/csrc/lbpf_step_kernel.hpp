@@ -89,9 +89,11 @@ template <class E> __device__ __forceinline__ void stb(E *base, unsigned boff, E
 constexpr int kStagedAniso = 32;
 
 // Minimum waves per SIMD the register allocator must leave room for (2D
-// kernels with the index field: 4, which they fit without spills).
-template <int DIM, int TY, class ST, bool IDS> constexpr int min_waves() {
-  return DIM == 2 ? (std::is_same<ST, StF64>::value ? 3 : (IDS ? 4 : 5)) : (std::is_same<ST, StF64>::value ? 2 : (TY == 8 ? 4 : 3));
+// kernels with the index field or the mirror planes: 4, which they fit
+// without spills).
+template <int DIM, int TY, class ST, bool IDS, bool MIR> constexpr int min_waves() {
+  return DIM == 2 ? (std::is_same<ST, StF64>::value ? 3 : ((IDS || MIR) ? 4 : 5))
+                  : (std::is_same<ST, StF64>::value ? 2 : (TY == 8 ? 4 : 3));
 }
 
 // BATCH = false: one simulation (sd_arg); the work-group id gives the tile and
@@ -108,7 +110,7 @@ template <int DIM, int TY, class ST, bool IDS> constexpr int min_waves() {
 // Sec. 4.2 through the moment of Eq. Grad_DF-Centree; the gradient then reaches
 // two nodes, so the phi ring keeps a 3-node halo and one more plane.
 template <int K, int TY, class ST, bool IDS, bool BATCH, bool MIR, int GR>
-__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(min_waves<LatOf<K>::DIM, TY, ST, IDS>(), 8))) void
+__global__ __launch_bounds__(64 * TY) __attribute__((amdgpu_waves_per_eu(min_waves<LatOf<K>::DIM, TY, ST, IDS, MIR>(), 8))) void
 step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const BatchItem *__restrict__ items,
             int n_items) {
   constexpr int DIM = LatOf<K>::DIM;
