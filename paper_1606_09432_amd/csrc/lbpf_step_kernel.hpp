@@ -204,6 +204,13 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
     // halo) stay inside the box without wrapping: plain constant offsets there
     const bool xy_in1 = x0 >= 1 && x0 + TX + 1 <= sd.nx && (DIM == 2 || (y0 >= 1 && y0 + TY + 1 <= sd.nyp));
     const bool xy_in2 = x0 >= 2 && x0 + TX + 2 <= sd.nx && (DIM == 2 || (y0 >= 2 && y0 + TY + 2 <= sd.nyp));
+    // a tile at a zero-flux wall x = 0 or x = nx - 1 whose pulls stay inside
+    // the box along yp (and m, per plane) takes the constant-offset loads too;
+    // a lane on the wall reads an in-box node in place of a source beyond it,
+    // and the bounce-back below replaces that population, knowing it from two
+    // lane flags
+    const bool x_walls_only = !per && !mir_tile && !xy_in1 &&
+                              (DIM == 2 || (y0 >= 1 && y0 + TY + 1 <= sd.nyp));
 
     // (no __restrict__: the g loads of B must stay below the barrier that ends A,
     // where they would otherwise be hoisted and held in registers through A)
@@ -580,6 +587,8 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
     const int gx_o = x0 + tx;
     const int gy_o = y0 + ty;
     const bool own = in_range(gx_o, sd.nx) && (DIM == 2 || in_range(gy_o, sd.nyp));
+    // on a wall x = 0 / x = nx - 1 of such a tile (false on every other tile)
+    const bool at_x0 = x_walls_only && gx_o == 0, at_x1 = x_walls_only && gx_o == sd.nx - 1;
     const int nodeo = hy_o * HX + hx_o;
     const int pco = (hy_o + PYO) * PX + (hx_o + PXO);
 
@@ -592,7 +601,7 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       S gy_r[QP], gx_r[QP];
       bool unk[QP];
       // one batch of loads: g_i(y) and g_i(y - e_i)
-      const bool fast = xy_in1 && m >= 1 && m + 1 < sd.nm;
+      const bool fast = (xy_in1 || x_walls_only) && m >= 1 && m + 1 < sd.nm;
       // Each population is read twice, as the own value of its node and as the
       // upstream value of the node downstream. The second of the two reads
       // carries the non-temporal hint, so that L2 keeps the lines still to be
@@ -601,10 +610,17 @@ step_kernel(SimDev sd_arg, TileDev tc, const SimDev *__restrict__ sims, const Ba
       // plane earlier). The choice is made at compile time; a hinted and a
       // plain load of one address would be merged into a plain one.
       auto load_fast = [&]() {
+        // a lane on a wall reads the source one node further in along x (its
+        // own column): an address inside the box, for a value the bounce-back
+        // replaces
+        const unsigned iyb_p = at_x0 ? iyb + (unsigned)sizeof(S) : iyb;  // sources of e_x = +1
+        const unsigned iyb_m = at_x1 ? iyb - (unsigned)sizeof(S) : iyb;  // sources of e_x = -1
         static_for<0, QP>([&](auto ic) {
           constexpr int i = decltype(ic)::value;
-          unk[i] = false;
-          const unsigned bx = iyb + boff_of(ex<LP, DIM>(i), ey<LP, DIM>(i), em<LP, DIM>(i), sizeof(S));
+          constexpr int cx = ex<LP, DIM>(i);
+          unk[i] = (cx == 1 && at_x0) || (cx == -1 && at_x1);
+          const unsigned bx = (cx == 1 ? iyb_p : (cx == -1 ? iyb_m : iyb)) +
+                              boff_of(cx, ey<LP, DIM>(i), em<LP, DIM>(i), sizeof(S));
           if constexpr (em<LP, DIM>(i) == -1)
             gy_r[i] = ldb_nt(gfield(i), iyb);
           else
