@@ -316,7 +316,8 @@ void units(const lbpf_config &c, SimHost &s) {
 // of 4 x 64 per CU) 4 rows; FP32 arithmetic 12 rows (one work-group of 12
 // waves per CU, 3 per SIMD: the 2-node halo of the coefficient pass then costs
 // 1/3 of what it costs at 4 rows).  3D: 32 planes per work-group, fewer when
-// that would leave fewer than 2048 work-groups.  2D: about 16384 work-groups,
+// that would leave fewer than 2048 work-groups, 64 on 12-row tiles when that
+// still leaves 2560 or more.  2D: about 16384 work-groups,
 // at least 16 rows each (8 in FP64).
 void default_tile(SimHost &s) {
   TileDev &t = s.tile;
@@ -327,6 +328,10 @@ void default_tile(SimHost &s) {
   long long ch;
   if (s.dim == 3) {
     ch = std::min<long long>(32, std::max<long long>(8, s.nm * tiles / 2048));
+    // 12-row tiles on boxes large enough to keep 10 work-groups per CU at 64
+    // planes: 64 planes (fewer ring warm-up planes per node; at 512^3 0.8-1.1 %
+    // faster in every FP32-arithmetic form, at 384^3 slower)
+    if (t.ty == 12 && s.nm * tiles / 64 >= 2560) ch = 64;
   } else {
     ch = std::max<long long>(s.storage == LBPF_FP64 ? 8 : 16, (s.nm * tiles + 16383) / 16384);
   }
